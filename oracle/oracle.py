@@ -1,0 +1,157 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle.c) plus the small pieces that
+are easiest to state in numpy.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the package smoke check
+and by the benchmark's CPU-baseline leg.  The product path (the HIP library
+and its Python binding) never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.c")
+
+_dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i64 = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc -O2 (no fast-math) and OpenMP."""
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=HERE)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        d = C.c_double
+        for name, nargs in (("or_rf", 3), ("or_rd", 3), ("or_rj", 4), ("or_ellk", 1),
+                            ("or_elle", 1), ("or_ellpi", 2)):
+            f = getattr(L, name); f.restype = d; f.argtypes = [d] * nargs
+        L.or_ma_alpha.restype = C.c_int
+        L.or_ma_alpha.argtypes = [d, d, _dp]
+        L.or_ma_flux.restype = d
+        L.or_ma_flux.argtypes = [d, d, d, d]
+        L.or_gimenez_alpha.restype = None
+        L.or_gimenez_alpha.argtypes = [d, d, C.c_int, C.c_int, _dp]
+        L.or_gimenez_flux.restype = d
+        L.or_gimenez_flux.argtypes = [d, d, _dp, C.c_int, C.c_int]
+        L.or_orbit_z.restype = d
+        L.or_orbit_z.argtypes = [d] * 7
+        L.or_last_newton_iters.restype = C.c_int
+        L.or_num_threads.restype = C.c_int
+        L.or_num_threads.argtypes = [C.c_int32]
+        L.or_lc_batch.restype = C.c_int
+        L.or_lc_batch.argtypes = [C.c_int32, _dp, _i64, _i64, _dp, _dp, _dp, _dp, _dp, _dp,
+                                  _dp, _i32, _i32, _dp, _dp, C.c_int32, _i64, C.c_int32,
+                                  C.c_int32, _dp, C.c_int32]
+        _lib = L
+    return _lib
+
+
+# -- scalar / elementwise helpers ----------------------------------------------------
+
+def ellk(m): return lib().or_ellk(float(m))
+def elle(m): return lib().or_elle(float(m))
+def ellpi(n, m): return lib().or_ellpi(float(n), float(m))
+def rf(x, y, z): return lib().or_rf(float(x), float(y), float(z))
+def rd(x, y, z): return lib().or_rd(float(x), float(y), float(z))
+def rj(x, y, z, p): return lib().or_rj(float(x), float(y), float(z), float(p))
+
+
+def ma_alpha(z, k):
+    """(lambda_e, lambda_d + 2/3 Theta(k-z), eta_d) and the case number."""
+    out = np.zeros(3)
+    cs = lib().or_ma_alpha(float(z), float(k), out)
+    return out, cs
+
+
+def ma_alpha_many(z, k):
+    z = np.broadcast_to(np.asarray(z, np.float64), np.broadcast(z, k).shape).ravel()
+    k = np.broadcast_to(np.asarray(k, np.float64), z.shape).ravel()
+    res = np.empty((z.size, 3))
+    out = np.zeros(3)
+    L = lib()
+    for i in range(z.size):
+        L.or_ma_alpha(z[i], k[i], out)
+        res[i] = out
+    return res
+
+
+def ma_flux(z, k, u1, u2):
+    z = np.atleast_1d(np.asarray(z, np.float64))
+    L = lib()
+    return np.array([L.or_ma_flux(zz, float(k), float(u1), float(u2)) for zz in z])
+
+
+def gimenez_alpha(z, k, nldc, npol):
+    out = np.zeros(nldc + 1)
+    lib().or_gimenez_alpha(float(z), float(k), int(nldc), int(npol), out)
+    return out
+
+
+def gimenez_flux(z, k, u, npol):
+    u = np.ascontiguousarray(u, np.float64)
+    z = np.atleast_1d(np.asarray(z, np.float64))
+    L = lib()
+    return np.array([L.or_gimenez_flux(zz, float(k), u, len(u), int(npol)) for zz in z])
+
+
+def orbit_z(t, t0, P, aR, b, e, w):
+    t = np.atleast_1d(np.asarray(t, np.float64))
+    L = lib()
+    return np.array([L.or_orbit_z(tt, t0, P, aR, b, e, w) for tt in t])
+
+
+def quadratic_to_general(u1, u2):
+    """Quadratic (a, b) -> general-law (u_1, u_2) = (a + 2b, -b) (Sect. 2.1.2)."""
+    return np.array([u1 + 2.0 * u2, -u2])
+
+
+def lc_batch(batch, model: int = 0, npol: int = 50, u=None, nthreads: int = 0):
+    """Supersampled ragged batch in FP64.  model 0: quadratic Mandel-Agol with
+    batch['u'] = (u1, u2); model 1: Gimenez with general-law ``u`` (default:
+    the quadratic coefficients transformed)."""
+    if u is None:
+        u = batch["u"] if model == 0 else np.stack(
+            [batch["u"][:, 0] + 2 * batch["u"][:, 1], -batch["u"][:, 1]], 1)
+    u = np.ascontiguousarray(u, np.float64)
+    nldc = u.shape[1]
+    flux = np.empty(batch["n_flux"])
+    rc = lib().or_lc_batch(
+        len(batch["t_start"]), batch["t"], batch["t_start"], batch["t_count"],
+        batch["t0"], batch["P"], batch["aR"], batch["b"], batch["e"], batch["w"],
+        batch["t_exp"], batch["nss"], batch["band_off"], batch["k"], u, nldc,
+        batch["flux_off"], model, npol, flux, nthreads)
+    if rc != 0:
+        raise ValueError("oracle lc_batch: bad arguments")
+    return flux
+
+
+def num_threads(nthreads: int = 0) -> int:
+    return lib().or_num_threads(nthreads)
+
+
+def surrogate_targets(zk):
+    """The three limb-darkening-factored Mandel-Agol functions
+    (alpha_0, alpha_1, alpha_0 - alpha_2) = (lambda_e, lambda_d + 2/3 Theta,
+    eta_d) at each (z, k) row; zero for z >= 1 + k."""
+    zk = np.asarray(zk, np.float64)
+    return ma_alpha_many(zk[:, 0], zk[:, 1])
