@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the transit-model hot path on one MI355X.
+
+A step is one pt_lc_batch call over the long-cadence batch: 256 eccentric
+parameter vectors x 200,000 exposure times (100 transits) x 10 subsamples of
+a 29.4-minute exposure, quadratic Mandel-Agol in the float path (orbit ->
+z -> overlap functions -> limb darkening -> subsample mean), i.e. 5.12e8
+model points per step with the inputs resident in HBM.
+
+Prints one JSON line (see the keys below).  The FP64 path, the Gimenez model
+on the spectrophotometric batch and (when installed) the surrogate are
+timed on the side and reported under "paths".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per unit, counted from the arithmetic of the path (FMA = 2
+# flops, add/mul/compare-free ops = 1, each square root, reciprocal and
+# trigonometric call = 1); see the flop-count notes in the design document.
+FLOP_ORBIT = 110          # per (exposure, subsample): phase, Newton solve, z
+FLOP_MA_IN = 330          # per (band, exposure, subsample) with z < 1 + k
+FLOP_MA_OUT = 3           # per (band, exposure, subsample) out of transit
+FLOP_GIM_TERM = 6         # per Clenshaw term (3 FMA) per alpha_n
+FLOP_GIM_POINT = 20       # per in-transit point: c, powers, combination
+PEAK_ALU = 78.6e12        # FP32/FP64 non-packed VALU FMA peak (see design notes)
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-side", action="store_true", help="skip the side paths")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3
+
+
+def count_units(pt, batch):
+    """Orbit points and in-transit (band, exposure, subsample) points, from
+    z on the GPU (pt_orbit_z per light curve over its subsample times)."""
+    import torch
+    n_orbit = 0
+    n_in = 0
+    for i in range(len(batch["t_start"])):
+        s, c, n = batch["t_start"][i], batch["t_count"][i], int(batch["nss"][i])
+        t = torch.as_tensor(batch["t"][s:s + c], device="cuda")
+        off = torch.as_tensor((np.arange(n) + 0.5) / n - 0.5, device="cuda") * float(batch["t_exp"][i])
+        ts = (t[:, None] + off[None, :]).reshape(-1).contiguous()
+        z = pt.orbit_z(ts, batch["t0"][i], batch["P"][i], batch["aR"][i], batch["b"][i],
+                       batch["e"][i], batch["w"][i], prec="fp64")
+        n_orbit += ts.numel()
+        for bnd in range(batch["band_off"][i], batch["band_off"][i + 1]):
+            k = float(batch["k"][bnd])
+            n_in += int(((z >= 0) & (z < 1 + k)).sum().item())
+    return n_orbit, n_in
+
+
+def cpu_baseline(batch, seconds):
+    from oracle import oracle as O
+    from paper_1504_07433_amd import workloads as W
+    nthreads = O.num_threads(0)
+    one = W.subset(batch, [0])
+    t0 = time.perf_counter()
+    O.lc_batch(one, model=0)
+    dt1 = time.perf_counter() - t0
+    m = int(np.clip(np.floor(seconds / max(dt1, 1e-3)), 1, len(batch["t_start"])))
+    sub = W.subset(batch, np.arange(m))
+    t0 = time.perf_counter()
+    O.lc_batch(sub, model=0)
+    dt = time.perf_counter() - t0
+    pts = W.n_points(sub)
+    return {"value": pts / dt, "unit": "points/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"first {m} of {len(batch['t_start'])} light curves of the same batch "
+                      f"({pts:.3g} points, {dt:.1f} s, FP64 quadratic Mandel-Agol)"}
+
+
+def sampled_error(pt, O, batch, flux, n=2000, model=0, npol=50, u=None, seed=0):
+    import torch
+    from tests.sampling import random_pairs, single_exposure_subset
+    pairs = random_pairs(batch, n, seed=seed)
+    sb, idx = single_exposure_subset(batch, pairs)
+    if u is not None:
+        sb["u"] = np.concatenate([u[batch["band_off"][l]:batch["band_off"][l + 1]] for l, _ in pairs])
+    got = flux[torch.as_tensor(idx, device=flux.device)].cpu().numpy().astype(np.float64)
+    ref = O.lc_batch(sb, model=model, npol=npol, u=None if u is None else sb["u"])
+    return float(np.abs(got - ref).max())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   f"(got {args.gpus}); see the sharding notes in DESIGN.md"}))
+        sys.exit(2)
+    import torch
+    from paper_1504_07433_amd import pthip, workloads as W
+    torch.cuda.set_device(0)
+
+    batch = W.config2()
+    db = pthip.DeviceBatch(batch)
+    points = W.n_points(batch)
+    flux = torch.empty(batch["n_flux"], dtype=torch.float32, device="cuda")
+    if args.autotune:
+        pthip.autotune(db, "ma", prec="fp32", out=flux)
+    step = lambda: pthip.lc_batch(db, "ma", prec="fp32", out=flux)
+    wall, gpu_s = timed(step, args.steps, args.warmup)
+    ms = wall / args.steps * 1e3
+    value = points * args.steps / wall
+    kernel_s = gpu_s / args.steps
+    tile_e, wg = pthip.launch_shape(db, "ma", prec="fp32")
+
+    n_orbit, n_in = count_units(pthip, batch)
+    n_out = points - n_in
+    flops = n_orbit * FLOP_ORBIT + n_in * FLOP_MA_IN + n_out * FLOP_MA_OUT
+    achieved = flops / kernel_s
+    hbm = (batch["t"].nbytes + batch["n_flux"] * 4 + 256 * 8 * 8)
+    line = {
+        "metric": "model points/sec (incl. supersamples) at max|dF|<=1e-5 vs FP64, surrogate vs plain",
+        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": batch["name"], "light_curves": 256, "exposures": int(batch["t_count"][0]),
+                   "subsamples": 10, "bands": 1, "model": "quadratic Mandel-Agol", "precision": "fp32 path",
+                   "points_per_step": points, "tile_exposures": tile_e, "workgroups": wg},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU, "traffic": None,
+                     "kernel": "k_lc_batch<fp32, MA> (+ prep)", "kernel_ms": kernel_s * 1e3,
+                     "algorithmic_flops_per_launch": flops, "orbit_points": n_orbit,
+                     "in_transit_points": n_in, "hbm_bytes_algorithmic": hbm,
+                     "hbm_frac": hbm / kernel_s / HBM_PEAK},
+    }
+    from oracle import oracle as O
+    line["max_abs_dF_sampled"] = sampled_error(pthip, O, batch, flux)
+    line["in_transit_fraction"] = n_in / points
+
+    if not args.no_side:
+        paths = {}
+        flux64 = torch.empty(batch["n_flux"], dtype=torch.float64, device="cuda")
+        w64, _ = timed(lambda: pthip.lc_batch(db, "ma", prec="fp64", out=flux64), max(2, args.steps // 5), 1)
+        s64 = max(2, args.steps // 5)
+        paths["ma_fp64_same_workload"] = {"points_per_s": points * s64 / w64, "ms_per_step": w64 / s64 * 1e3,
+                                          "max_abs_dF_sampled": sampled_error(pthip, O, batch, flux64, 1000)}
+        paths["fp32_over_fp64_speedup"] = paths["ma_fp64_same_workload"]["ms_per_step"] / ms
+        b3 = W.config3()
+        d3 = pthip.DeviceBatch(b3)
+        ug = np.stack([b3["u"][:, 0] + 2 * b3["u"][:, 1], -b3["u"][:, 1]], 1)
+        d3g = pthip.DeviceBatch(b3, u=ug)
+        p3 = W.n_points(b3)
+        f3 = torch.empty(b3["n_flux"], dtype=torch.float32, device="cuda")
+        w3, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="fp32", out=f3), 10, 2)
+        paths["ma_fp32_spectrophotometric"] = {"workload": b3["name"], "points_per_s": p3 * 10 / w3,
+                                               "ms_per_step": w3 / 10 * 1e3}
+        w3g, _ = timed(lambda: pthip.lc_batch(d3g, "gimenez", npol=50, prec="fp32", out=f3), 5, 1)
+        paths["gimenez50_fp32_spectrophotometric"] = {
+            "workload": b3["name"], "points_per_s": p3 * 5 / w3g, "ms_per_step": w3g / 5 * 1e3,
+            "max_abs_dF_sampled": sampled_error(pthip, O, b3, f3, 200, model=1, u=ug)}
+        line["paths"] = paths
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

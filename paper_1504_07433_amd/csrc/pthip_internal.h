@@ -1,0 +1,91 @@
+// pthip_internal.h -- structures shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "transit_math.h"
+
+namespace pt {
+
+// Per-passband constants of a batch, formed on the device each call.
+struct BandConst {
+  double kd;            // radius ratio
+  double wd[5];         // loss weights in double (MA: (1-c)/N, c/N, u2/N; Gimenez: C_0..C_N)
+  float wf[5];          // the same in float
+  float kf;             // radius ratio, float
+  float onepk;          // 1 + k (float), out-of-transit test
+  float omk;            // 1 - k (float)
+  float inv1pk;         // 1 / (1 + k) (float), Gimenez c = z/(1+k)
+  double inv1pkd;       // 1 / (1 + k) (double)
+  int32_t exact;        // k > 1/2: Mandel-Agol through the exact double path
+  int32_t valid;        // k > 0 and finite weights
+};
+
+// One unit of the persistent queue: exposures e0 .. e0+ne-1 of light curve lc.
+struct TileDesc {
+  int32_t lc;
+  int32_t e0;
+  int32_t ne;
+  int32_t pad;
+};
+
+enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2 };
+enum : int { kModelMA = 0, kModelGimenez = 1 };
+
+// Subsamples whose z values a wave keeps in LDS at once.
+constexpr int kZChunk = 16;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+// Everything the persistent batch kernel reads.
+struct BatchArgs {
+  const double* t;
+  const double* t0;
+  const double* P;
+  const double* aR;
+  const double* b;
+  const double* e;
+  const double* w;
+  const double* t_exp;
+  const double* k;
+  const double* u;
+  const int64_t* t_start;
+  const int64_t* t_count;
+  const int32_t* nss;
+  const int32_t* band_off;
+  const int64_t* flux_off;
+  const TileDesc* tiles;
+  OrbitConst* oc;       // [n_lc], written by the prep kernel
+  BandConst* bc;        // [n_band], written by the prep kernel
+  void* gtab;           // Gimenez per-band tables [n_band][nldc+1][npol] (float or double)
+  const void* grec;     // shared recurrence coefficients [(nldc+1)][npol][3]
+  const double* gaprime;  // A'_{n,j} [(nldc+1)][npol]
+  unsigned int* queue;  // [0] next tile (reset by the prep kernel)
+  void* flux;
+  int64_t n_tiles;
+  int32_t n_lc;
+  int32_t n_band;
+  int32_t nldc;
+  int32_t npol;
+  int32_t model;
+  // surrogate
+  const void* mlp;      // device MlpDev (bf16 weights) or null
+};
+
+// Launchers (defined in pthip_kernels.hip).
+hipError_t launch_orbit_z(const double* t, int64_t n, const OrbitConst& o, int prec, double* z,
+                          hipStream_t s);
+hipError_t launch_ma_quad(const double* z, int64_t n, double k, const double* u, int nb, int prec,
+                          double* flux, hipStream_t s);
+hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
+                             const double* aprime, void* tab, int prec, hipStream_t s);
+hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u, int nldc, int nb,
+                          int npol, const void* tab, const void* rec, int prec, double* flux,
+                          hipStream_t s);
+
+// Prep (orbit and band constants, queue reset), Gimenez tables when needed,
+// and the persistent kernel on `workgroups` workgroups of kBlock threads.
+hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups, hipStream_t s);
+
+}  // namespace pt

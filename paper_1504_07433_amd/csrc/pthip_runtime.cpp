@@ -1,0 +1,619 @@
+// pthip_runtime.cpp -- host side of libpthip.so: argument validation, error
+// reporting, device-resident coefficient tables, batch plans (tile queue,
+// launch shape, captured graph) and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pthip.h"
+#include "pthip_internal.h"
+
+namespace pt {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static pt_status fail(pt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define PT_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(PT_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+static bool fault_injected() {
+  const char* v = getenv("PT_FAULT_INJECT");
+  return v && strcmp(v, "hip") == 0;
+}
+
+static pt_status ok() {
+  g_err.clear();
+  return PT_OK;
+}
+
+static std::mutex g_mu;
+
+static int current_device() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return -1;
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Device buffers owned by the library
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  int dev = -1;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) {
+      int cur = current_device();
+      if (dev >= 0 && cur != dev) hipSetDevice(dev);
+      hipFree(p);
+      if (dev >= 0 && cur != dev && cur >= 0) hipSetDevice(cur);
+    }
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n && p) return hipSuccess;
+    release();
+    dev = current_device();
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e == hipSuccess) n = bytes;
+    return e;
+  }
+};
+
+// Gimenez k-independent tables for (nldc, npol): A'_{n,j} (double) and the
+// Clenshaw recurrence coefficients {A_j, B_j, C_{j+1}} in float and double.
+struct GimTables {
+  DevBuf aprime, rec32, rec64;
+};
+static std::map<std::tuple<int, int, int>, std::unique_ptr<GimTables>> g_gim;
+
+static pt_status gim_tables(int nldc, int npol, GimTables** out) {
+  const int dev = current_device();
+  auto key = std::make_tuple(dev, nldc, npol);
+  auto it = g_gim.find(key);
+  if (it != g_gim.end()) {
+    *out = it->second.get();
+    return PT_OK;
+  }
+  const size_t nn = (size_t)(nldc + 1) * npol;
+  std::vector<double> ap(nn), r64(3 * nn);
+  std::vector<float> r32(3 * nn);
+  for (int n = 0; n <= nldc; ++n)
+    for (int j = 0; j < npol; ++j) {
+      ap[n * npol + j] = gimenez_aprime(n, j);
+      double A, B, Cn;
+      gimenez_rec_coef(n, j, &A, &B, &Cn);
+      const size_t o = 3 * (size_t)(n * npol + j);
+      r64[o] = A; r64[o + 1] = B; r64[o + 2] = Cn;
+      r32[o] = float(A); r32[o + 1] = float(B); r32[o + 2] = float(Cn);
+    }
+  auto t = std::make_unique<GimTables>();
+  PT_HIP(t->aprime.ensure(nn * sizeof(double)));
+  PT_HIP(t->rec64.ensure(3 * nn * sizeof(double)));
+  PT_HIP(t->rec32.ensure(3 * nn * sizeof(float)));
+  PT_HIP(hipMemcpy(t->aprime.p, ap.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+  PT_HIP(hipMemcpy(t->rec64.p, r64.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice));
+  PT_HIP(hipMemcpy(t->rec32.p, r32.data(), 3 * nn * sizeof(float), hipMemcpyHostToDevice));
+  *out = t.get();
+  g_gim[key] = std::move(t);
+  return PT_OK;
+}
+
+static int cu_count() {
+  int dev = current_device();
+  int cu = 0;
+  if (dev < 0 || hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -1;
+  return cu;
+}
+
+static bool valid_prec(pt_prec p) { return p == PT_PREC_FP64 || p == PT_PREC_FP32 || p == PT_PREC_SURROGATE; }
+
+// ---------------------------------------------------------------------------
+// Batch plans
+// ---------------------------------------------------------------------------
+struct LaunchShape {
+  int tile_e = 256;
+  int workgroups = 0;
+};
+
+struct TileSet {
+  DevBuf tiles;
+  int64_t n_tiles = 0;
+};
+
+struct Plan {
+  int dev = -1;
+  int32_t n_lc = 0, n_band = 0, nldc = 0, npol = 0, model = 0, prec = 0;
+  std::vector<int64_t> t_count;
+  std::vector<int32_t> nss, band_off;
+  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, oc, bc, gtab, queue;
+  std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
+  LaunchShape shape;
+  bool tuned = false;
+  // captured graph for the last argument set
+  hipGraphExec_t exec = nullptr;
+  BatchArgs exec_args{};
+  int exec_workgroups = 0;
+  hipStream_t capture_stream = nullptr;
+  ~Plan() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (capture_stream) hipStreamDestroy(capture_stream);
+  }
+};
+
+static std::map<std::string, std::unique_ptr<Plan>> g_plans;
+
+static void hash_bytes(std::string& key, const void* p, size_t n) {
+  // FNV-1a over the contents, appended as hex; plus the length
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  char buf[40];
+  snprintf(buf, sizeof buf, "%016llx:%zu;", (unsigned long long)h, n);
+  key += buf;
+}
+
+static std::string plan_key(const pt_batch* b, int model, int npol, int prec) {
+  char head[128];
+  snprintf(head, sizeof head, "d%d m%d p%d q%d n%d l%d t%lld f%lld|", current_device(), model,
+           model == PT_MODEL_GIMENEZ ? npol : 0, prec, b->n_lc, b->nldc, (long long)b->n_t,
+           (long long)b->n_flux);
+  std::string key(head);
+  const size_t n = (size_t)b->n_lc;
+  hash_bytes(key, b->t_start, n * sizeof(int64_t));
+  hash_bytes(key, b->t_count, n * sizeof(int64_t));
+  hash_bytes(key, b->nss, n * sizeof(int32_t));
+  hash_bytes(key, b->band_off, (n + 1) * sizeof(int32_t));
+  hash_bytes(key, b->flux_off, n * sizeof(int64_t));
+  return key;
+}
+
+static pt_status validate_batch(const pt_batch* b, pt_model model, int32_t npol, pt_prec prec) {
+  if (!b) return fail(PT_ERR_ARG, "batch is NULL");
+  if (model != PT_MODEL_MA_QUAD && model != PT_MODEL_GIMENEZ) return fail(PT_ERR_ARG, "unknown model %d", (int)model);
+  if (!valid_prec(prec)) return fail(PT_ERR_ARG, "unknown precision %d", (int)prec);
+  if (b->n_lc < 0) return fail(PT_ERR_ARG, "n_lc = %d < 0", b->n_lc);
+  if (model == PT_MODEL_MA_QUAD && b->nldc != 2)
+    return fail(PT_ERR_ARG, "quadratic Mandel-Agol needs nldc = 2 (u1, u2), got %d", b->nldc);
+  if (model == PT_MODEL_GIMENEZ && (b->nldc < 1 || b->nldc > 4))
+    return fail(PT_ERR_ARG, "Gimenez needs 1 <= nldc <= 4, got %d", b->nldc);
+  if (model == PT_MODEL_GIMENEZ && (npol < 1 || npol > 512))
+    return fail(PT_ERR_ARG, "npol = %d outside 1..512", npol);
+  if (b->n_t < 0 || b->n_flux < 0) return fail(PT_ERR_ARG, "negative n_t or n_flux");
+  if (b->n_lc == 0) return PT_OK;
+  if (!b->t_start || !b->t_count || !b->nss || !b->band_off || !b->flux_off)
+    return fail(PT_ERR_ARG, "a host shape array is NULL");
+  if (!b->t0 || !b->P || !b->aR || !b->b || !b->e || !b->w || !b->t_exp)
+    return fail(PT_ERR_ARG, "a device parameter array is NULL");
+  if (b->n_t > 0 && !b->t) return fail(PT_ERR_ARG, "t is NULL");
+  if (b->band_off[0] < 0) return fail(PT_ERR_ARG, "band_off[0] < 0");
+  struct Blk { int64_t off, len; int32_t lc; };
+  std::vector<Blk> blocks;
+  blocks.reserve(b->n_lc);
+  for (int32_t i = 0; i < b->n_lc; ++i) {
+    const int64_t c = b->t_count[i], s = b->t_start[i];
+    if (c < 0) return fail(PT_ERR_ARG, "light curve %d: t_count = %lld < 0", i, (long long)c);
+    if (c > 0x7fffffffLL) return fail(PT_ERR_ARG, "light curve %d: more than 2^31-1 exposures", i);
+    if (s < 0 || s + c > b->n_t)
+      return fail(PT_ERR_ARG, "light curve %d: times [%lld, %lld) outside the pool of %lld", i,
+                  (long long)s, (long long)(s + c), (long long)b->n_t);
+    if (b->nss[i] < 1) return fail(PT_ERR_ARG, "light curve %d: nss = %d < 1", i, b->nss[i]);
+    if (b->band_off[i + 1] < b->band_off[i])
+      return fail(PT_ERR_ARG, "light curve %d: band_off decreases", i);
+    const int64_t nb = b->band_off[i + 1] - b->band_off[i];
+    const int64_t fo = b->flux_off[i];
+    if (fo < 0 || fo + nb * c > b->n_flux)
+      return fail(PT_ERR_ARG, "light curve %d: output block [%lld, %lld) outside n_flux = %lld", i,
+                  (long long)fo, (long long)(fo + nb * c), (long long)b->n_flux);
+    if (nb * c > 0) blocks.push_back({fo, nb * c, i});
+  }
+  const int64_t n_band = b->band_off[b->n_lc];
+  if (n_band > 0 && (!b->k || !b->u)) return fail(PT_ERR_ARG, "k or u is NULL");
+  std::sort(blocks.begin(), blocks.end(), [](const Blk& x, const Blk& y) { return x.off < y.off; });
+  for (size_t i = 1; i < blocks.size(); ++i)
+    if (blocks[i].off < blocks[i - 1].off + blocks[i - 1].len)
+      return fail(PT_ERR_ARG, "output blocks of light curves %d and %d overlap", blocks[i - 1].lc,
+                  blocks[i].lc);
+  return PT_OK;
+}
+
+static pt_status build_tiles(Plan* p, int tile_e, TileSet** out) {
+  auto it = p->tilesets.find(tile_e);
+  if (it != p->tilesets.end()) {
+    *out = it->second.get();
+    return PT_OK;
+  }
+  struct W { double work; TileDesc t; };
+  std::vector<W> v;
+  for (int32_t lc = 0; lc < p->n_lc; ++lc) {
+    const int64_t c = p->t_count[lc];
+    const int nb = p->band_off[lc + 1] - p->band_off[lc];
+    if (nb == 0) continue;
+    for (int64_t e0 = 0; e0 < c; e0 += tile_e) {
+      const int ne = (int)std::min<int64_t>(tile_e, c - e0);
+      // wave iterations x subsamples x bands (+ the orbit per subsample)
+      const double work = double((ne + kWave - 1) / kWave) * p->nss[lc] * (nb + 1.0);
+      v.push_back({work, TileDesc{lc, (int32_t)e0, ne, 0}});
+    }
+  }
+  // longest first; equal work keeps light-curve order for cache locality
+  std::stable_sort(v.begin(), v.end(), [](const W& a, const W& b) { return a.work > b.work; });
+  std::vector<TileDesc> tiles(v.size());
+  for (size_t i = 0; i < v.size(); ++i) tiles[i] = v[i].t;
+  auto ts = std::make_unique<TileSet>();
+  ts->n_tiles = (int64_t)tiles.size();
+  PT_HIP(ts->tiles.ensure(std::max<size_t>(1, tiles.size()) * sizeof(TileDesc)));
+  if (!tiles.empty())
+    PT_HIP(hipMemcpy(ts->tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
+  *out = ts.get();
+  p->tilesets[tile_e] = std::move(ts);
+  return PT_OK;
+}
+
+static int default_tile(const pt_batch* b) {
+  // aim for several tiles per resident wave; small light curves need small tiles
+  int64_t expo = 0;
+  for (int32_t i = 0; i < b->n_lc; ++i) expo += b->t_count[i] * (b->band_off[i + 1] > b->band_off[i]);
+  const int cu = std::max(1, cu_count());
+  const int64_t waves = (int64_t)cu * 8;
+  int te = 1024;
+  while (te > kWave && expo / te < 4 * waves) te /= 2;
+  return te;
+}
+
+static std::map<std::string, LaunchShape> g_tuned;  // autotuned shapes by plan key
+
+static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_prec prec, Plan** out,
+                          std::string* key_out) {
+  std::string key = plan_key(b, model, npol, prec);
+  if (key_out) *key_out = key;
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return PT_OK;
+  }
+  auto p = std::make_unique<Plan>();
+  p->dev = current_device();
+  p->n_lc = b->n_lc;
+  p->n_band = b->n_lc > 0 ? b->band_off[b->n_lc] : 0;
+  p->nldc = b->nldc;
+  p->npol = model == PT_MODEL_GIMENEZ ? npol : 0;
+  p->model = model;
+  p->prec = prec;
+  const size_t n = (size_t)b->n_lc;
+  p->t_count.assign(b->t_count, b->t_count + n);
+  p->nss.assign(b->nss, b->nss + n);
+  p->band_off.assign(b->band_off, b->band_off + n + 1);
+  PT_HIP(p->d_t_start.ensure(std::max<size_t>(1, n) * 8));
+  PT_HIP(p->d_t_count.ensure(std::max<size_t>(1, n) * 8));
+  PT_HIP(p->d_nss.ensure(std::max<size_t>(1, n) * 4));
+  PT_HIP(p->d_band_off.ensure((n + 1) * 4));
+  PT_HIP(p->d_flux_off.ensure(std::max<size_t>(1, n) * 8));
+  if (n) {
+    PT_HIP(hipMemcpy(p->d_t_start.p, b->t_start, n * 8, hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(p->d_t_count.p, b->t_count, n * 8, hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(p->d_nss.p, b->nss, n * 4, hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(p->d_band_off.p, b->band_off, (n + 1) * 4, hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(p->d_flux_off.p, b->flux_off, n * 8, hipMemcpyHostToDevice));
+  }
+  PT_HIP(p->oc.ensure(std::max<size_t>(1, n) * sizeof(OrbitConst)));
+  PT_HIP(p->bc.ensure(std::max<size_t>(1, (size_t)p->n_band) * sizeof(BandConst)));
+  PT_HIP(p->queue.ensure(64));
+  PT_HIP(hipMemset(p->queue.p, 0, 64));
+  if (model == PT_MODEL_GIMENEZ) {
+    const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
+    PT_HIP(p->gtab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * npol * es));
+  }
+  auto tu = g_tuned.find(key);
+  if (tu != g_tuned.end()) {
+    p->shape = tu->second;
+    p->tuned = true;
+  } else {
+    p->shape.tile_e = default_tile(b);
+    p->shape.workgroups = std::max(1, cu_count()) * 2;
+  }
+  PT_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+  *out = p.get();
+  g_plans[key] = std::move(p);
+  return PT_OK;
+}
+
+static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, BatchArgs* a) {
+  TileSet* ts = nullptr;
+  pt_status st = build_tiles(p, tile_e, &ts);
+  if (st != PT_OK) return st;
+  memset(a, 0, sizeof *a);
+  a->t = b->t; a->t0 = b->t0; a->P = b->P; a->aR = b->aR; a->b = b->b; a->e = b->e; a->w = b->w;
+  a->t_exp = b->t_exp; a->k = b->k; a->u = b->u;
+  a->t_start = (const int64_t*)p->d_t_start.p;
+  a->t_count = (const int64_t*)p->d_t_count.p;
+  a->nss = (const int32_t*)p->d_nss.p;
+  a->band_off = (const int32_t*)p->d_band_off.p;
+  a->flux_off = (const int64_t*)p->d_flux_off.p;
+  a->tiles = (const TileDesc*)ts->tiles.p;
+  a->n_tiles = ts->n_tiles;
+  a->oc = (OrbitConst*)p->oc.p;
+  a->bc = (BandConst*)p->bc.p;
+  a->queue = (unsigned int*)p->queue.p;
+  a->flux = flux;
+  a->n_lc = p->n_lc;
+  a->n_band = p->n_band;
+  a->nldc = p->nldc;
+  a->npol = p->npol;
+  a->model = p->model;
+  if (p->model == PT_MODEL_GIMENEZ) {
+    GimTables* g = nullptr;
+    st = gim_tables(p->nldc, p->npol, &g);
+    if (st != PT_OK) return st;
+    a->gtab = p->gtab.p;
+    a->grec = p->prec == PT_PREC_FP64 ? g->rec64.p : g->rec32.p;
+    a->gaprime = (const double*)g->aprime.p;
+  }
+  return PT_OK;
+}
+
+static bool use_graph() {
+  const char* v = getenv("PT_NO_GRAPH");
+  return !(v && v[0] == '1');
+}
+
+static pt_status run_plan(Plan* p, const BatchArgs& a, int workgroups, hipStream_t s) {
+  const int prec = p->prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
+  if (!use_graph()) {
+    PT_HIP(launch_batch(a, prec, p->model, workgroups, s));
+    return PT_OK;
+  }
+  if (!p->exec || memcmp(&p->exec_args, &a, sizeof a) != 0 || p->exec_workgroups != workgroups) {
+    hipGraph_t g = nullptr;
+    PT_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batch(a, prec, p->model, workgroups, p->capture_stream);
+    hipError_t ce = hipStreamEndCapture(p->capture_stream, &g);
+    if (le != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return fail(PT_ERR_HIP, "launch during capture: %s", hipGetErrorString(le));
+    }
+    if (ce != hipSuccess) return fail(PT_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+    if (p->exec) {
+      hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
+    }
+    hipError_t ie = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      p->exec = nullptr;
+      return fail(PT_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    }
+    p->exec_args = a;
+    p->exec_workgroups = workgroups;
+  }
+  PT_HIP(hipGraphLaunch(p->exec, s));
+  return PT_OK;
+}
+
+}  // namespace pt
+
+using namespace pt;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pt_version(void) { return "pthip 1.0 gfx950"; }
+
+const char* pt_last_error(void) { return g_err.c_str(); }
+
+void pt_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans.clear();
+  g_gim.clear();
+  g_tuned.clear();
+}
+
+int pt_device_cu_count(void) { return cu_count(); }
+
+pt_status pt_orbit_z(const double* t, int64_t n, double t0, double P, double aR, double b, double e,
+                     double w, pt_prec prec, double* z, void* stream) {
+  if (n < 0) return fail(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!t || !z)) return fail(PT_ERR_ARG, "t or z is NULL");
+  if (prec != PT_PREC_FP64 && prec != PT_PREC_FP32) return fail(PT_ERR_ARG, "prec must be FP64 or FP32");
+  if (!(P > 0)) return fail(PT_ERR_ARG, "period P = %g must be > 0", P);
+  if (!(aR > 0)) return fail(PT_ERR_ARG, "aR = %g must be > 0", aR);
+  if (!(e >= 0 && e < 1)) return fail(PT_ERR_ARG, "eccentricity e = %g outside [0, 1)", e);
+  if (!(b >= 0)) return fail(PT_ERR_ARG, "impact parameter b = %g must be >= 0", b);
+  if (!std::isfinite(t0) || !std::isfinite(w)) return fail(PT_ERR_ARG, "t0 and w must be finite");
+  const OrbitConst o = orbit_const(t0, P, aR, b, e, w, -1.0);
+  if (!o.valid) return fail(PT_ERR_ARG, "cos i = %g > 1 for b = %g, aR = %g, e = %g", o.cos_i, b, aR, e);
+  if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
+  PT_HIP(launch_orbit_z(t, n, o, prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32, z, (hipStream_t)stream));
+  return ok();
+}
+
+pt_status pt_ma_quad(const double* z, int64_t n, double k, const double* u, int32_t nb, pt_prec prec,
+                     double* flux, void* stream) {
+  if (n < 0) return fail(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (nb < 1) return fail(PT_ERR_ARG, "nb = %d < 1", nb);
+  if (!(k > 0) || !std::isfinite(k)) return fail(PT_ERR_ARG, "radius ratio k = %g must be > 0", k);
+  if (prec != PT_PREC_FP64 && prec != PT_PREC_FP32) return fail(PT_ERR_ARG, "prec must be FP64 or FP32");
+  if (n > 0 && (!z || !u || !flux)) return fail(PT_ERR_ARG, "z, u or flux is NULL");
+  if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
+  PT_HIP(launch_ma_quad(z, n, k, u, nb, prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32, flux,
+                        (hipStream_t)stream));
+  return ok();
+}
+
+pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int32_t nldc, int32_t nb,
+                     int32_t npol, pt_prec prec, double* flux, void* stream) {
+  if (n < 0) return fail(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (nb < 1) return fail(PT_ERR_ARG, "nb = %d < 1", nb);
+  if (nldc < 1 || nldc > 4) return fail(PT_ERR_ARG, "nldc = %d outside 1..4", nldc);
+  if (npol < 1 || npol > 512) return fail(PT_ERR_ARG, "npol = %d outside 1..512", npol);
+  if (!(k > 0) || !std::isfinite(k)) return fail(PT_ERR_ARG, "radius ratio k = %g must be > 0", k);
+  if (prec != PT_PREC_FP64 && prec != PT_PREC_FP32) return fail(PT_ERR_ARG, "prec must be FP64 or FP32");
+  if (n > 0 && (!z || !u || !flux)) return fail(PT_ERR_ARG, "z, u or flux is NULL");
+  if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
+  if (n == 0) return ok();
+  const int pr = prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
+  GimTables* g = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    pt_status st = gim_tables(nldc, npol, &g);
+    if (st != PT_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  void* tab = nullptr;
+  const size_t bytes = (size_t)(nldc + 1) * npol * (pr == kPrecFP64 ? 8 : 4);
+  PT_HIP(hipMallocAsync(&tab, bytes, s));
+  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double*)g->aprime.p, tab, pr, s);
+  hipError_t e2 = e1 == hipSuccess
+                      ? launch_gimenez(z, n, k, u, nldc, nb, npol, tab,
+                                       pr == kPrecFP64 ? g->rec64.p : g->rec32.p, pr, flux, s)
+                      : e1;
+  hipFreeAsync(tab, s);
+  if (e2 != hipSuccess) return fail(PT_ERR_HIP, "gimenez launch: %s", hipGetErrorString(e2));
+  return ok();
+}
+
+pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec, void* flux,
+                      void* stream) {
+  pt_status st = validate_batch(batch, model, npol, prec);
+  if (st != PT_OK) return st;
+  if (prec == PT_PREC_SURROGATE)
+    return fail(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
+  if (batch->n_lc == 0 || batch->band_off[batch->n_lc] == batch->band_off[0]) return ok();
+  if (batch->n_flux > 0 && !flux) return fail(PT_ERR_ARG, "flux is NULL");
+  if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Plan* p = nullptr;
+  st = get_plan(batch, model, npol, prec, &p, nullptr);
+  if (st != PT_OK) return st;
+  BatchArgs a;
+  st = fill_args(batch, p, p->shape.tile_e, flux, &a);
+  if (st != PT_OK) return st;
+  st = run_plan(p, a, p->shape.workgroups, (hipStream_t)stream);
+  if (st != PT_OK) return st;
+  return ok();
+}
+
+pt_status pt_batch_launch_shape(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec,
+                                int32_t* tile_exposures, int32_t* workgroups) {
+  pt_status st = validate_batch(batch, model, npol, prec);
+  if (st != PT_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const std::string key = plan_key(batch, model, npol, prec);
+  auto it = g_plans.find(key);
+  if (tile_exposures) *tile_exposures = it == g_plans.end() ? -1 : it->second->shape.tile_e;
+  if (workgroups) *workgroups = it == g_plans.end() ? -1 : it->second->shape.workgroups;
+  return ok();
+}
+
+pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec, void* flux,
+                      void* stream, char* report, size_t report_len) {
+  pt_status st = validate_batch(batch, model, npol, prec);
+  if (st != PT_OK) return st;
+  if (prec == PT_PREC_SURROGATE)
+    return fail(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
+  if (batch->n_lc == 0) return ok();
+  if (batch->n_flux > 0 && !flux) return fail(PT_ERR_ARG, "flux is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Plan* p = nullptr;
+  std::string key;
+  st = get_plan(batch, model, npol, prec, &p, &key);
+  if (st != PT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int cu = std::max(1, cu_count());
+  const int tiles[] = {64, 128, 256, 512, 1024, 2048};
+  const int wpc[] = {4, 8, 12, 16, 24};     // resident waves per CU requested
+  hipEvent_t e0, e1;
+  PT_HIP(hipEventCreate(&e0));
+  PT_HIP(hipEventCreate(&e1));
+  std::string rep = "{\"candidates\": [";
+  float best = 1e30f;
+  LaunchShape best_shape = p->shape;
+  const int prec_k = prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
+  bool first = true;
+  for (int te : tiles) {
+    BatchArgs a;
+    st = fill_args(batch, p, te, flux, &a);
+    if (st != PT_OK) break;
+    if (a.n_tiles == 0) continue;
+    for (int w : wpc) {
+      const int wg = cu * w / (kBlock / kWave);
+      if (wg < 1) continue;
+      if ((int64_t)wg * (kBlock / kWave) > 4 * a.n_tiles && w > 4) continue;  // mostly idle waves
+      float ms_best = 1e30f;
+      for (int rep_i = 0; rep_i < 3; ++rep_i) {
+        hipEventRecord(e0, s);
+        hipError_t le = launch_batch(a, prec_k, p->model, wg, s);
+        hipEventRecord(e1, s);
+        if (le != hipSuccess) { st = fail(PT_ERR_HIP, "autotune launch: %s", hipGetErrorString(le)); break; }
+        if (hipEventSynchronize(e1) != hipSuccess) { st = fail(PT_ERR_HIP, "autotune sync"); break; }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms_best = std::min(ms_best, ms);
+      }
+      if (st != PT_OK) break;
+      char buf[160];
+      snprintf(buf, sizeof buf, "%s{\"tile_exposures\": %d, \"waves_per_cu\": %d, \"workgroups\": %d, \"ms\": %.5f}",
+               first ? "" : ", ", te, w, wg, ms_best);
+      first = false;
+      rep += buf;
+      if (ms_best < best) {
+        best = ms_best;
+        best_shape.tile_e = te;
+        best_shape.workgroups = wg;
+      }
+    }
+    if (st != PT_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != PT_OK) return st;
+  p->shape = best_shape;
+  p->tuned = true;
+  g_tuned[key] = best_shape;
+  char buf[160];
+  snprintf(buf, sizeof buf, "], \"best\": {\"tile_exposures\": %d, \"workgroups\": %d, \"ms\": %.5f}}",
+           best_shape.tile_e, best_shape.workgroups, best);
+  rep += buf;
+  if (report && report_len > 0) {
+    strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return ok();
+}
+
+// Surrogate entry points: see pthip_mlp.hip.
+}  // extern "C"

@@ -1,0 +1,592 @@
+// transit_math.h -- device arithmetic of the transit-model hot path (gfx950).
+//
+// Inline functions shared by the HIP kernels: the orbit (Kepler's equation by
+// Newton's method, sky-projected distance z), the quadratic Mandel & Agol
+// (2002) overlap functions through Bulirsch's general complete elliptic
+// integral, and the Gimenez (2006) Jacobi series, as used by PyTransit
+// (Parviainen 2015, Sects. 2.1-2.2).  Everything is templated on the working
+// type: float for the bulk path, double for the exact path and for the
+// contact-point branches of the float path.
+//
+// The functions are __host__ __device__ so that the same arithmetic can be
+// exercised on the CPU when tuning tolerances; the library itself only runs
+// them on the GPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#define PT_HD __host__ __device__ __forceinline__
+
+namespace pt {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Primitive operations.  On the GPU the float versions use the 1-ulp hardware
+// square root and reciprocal (v_sqrt_f32, v_rcp_f32); the double versions use
+// the correctly rounded library routines.
+// ---------------------------------------------------------------------------
+template <class T> struct Num;
+
+template <> struct Num<float> {
+  PT_HD static float sqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return ::sqrtf(x);
+#endif
+  }
+  PT_HD static float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+  }
+  PT_HD static float atan2(float y, float x) { return ::atan2f(y, x); }
+  PT_HD static void sincos(float x, float* s, float* c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    ::sincosf(x, s, c);
+#else
+    *s = ::sinf(x); *c = ::cosf(x);
+#endif
+  }
+  static constexpr float cel_tol = 1e-4f;
+  static constexpr float newton_tol = 2e-7f;     // relative step at convergence
+  static constexpr float rot_limit = 0.5f;       // Taylor rotation valid below
+  static constexpr int newton_max = 12;
+};
+
+template <> struct Num<double> {
+  PT_HD static double sqrt(double x) { return ::sqrt(x); }
+  PT_HD static double rcp(double x) { return 1.0 / x; }
+  PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
+  PT_HD static void sincos(double x, double* s, double* c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    ::sincos(x, s, c);
+#else
+    *s = ::sin(x); *c = ::cos(x);
+#endif
+  }
+  static constexpr double cel_tol = 1e-10;
+  static constexpr double newton_tol = 4e-16;
+  static constexpr double rot_limit = 0.2;
+  static constexpr int newton_max = 40;
+};
+
+// Double-precision arithmetic with single-precision hardware seeds: the
+// reciprocal and square root start from v_rcp_f32 / v_rsq_f32 (relative error
+// ~1e-7) and take one Newton step in double, leaving ~1e-14.  On gfx950 a
+// double FMA issues at the rate of a float FMA, so this keeps the
+// cancellation-prone elliptic combinations at near-double accuracy for about
+// the cost of the float transcendentals.  Arguments must lie in the float
+// exponent range (1e-37 .. 1e37).
+struct NumFast {
+  PT_HD static double rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = (double)__builtin_amdgcn_rcpf((float)x);
+#else
+    double r = (double)(1.0f / (float)x);
+#endif
+    const double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  }
+  PT_HD static double sqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = (double)__builtin_amdgcn_rsqf((float)x);
+#else
+    const double y = (double)(1.0f / ::sqrtf((float)x));
+#endif
+    const double s = x * y;
+    const double r = fma(-s, s, x);          // x - s^2
+    return fma(0.5 * y, r, s);
+  }
+  PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
+  PT_HD static void sincos(double x, double* s, double* c) { Num<double>::sincos(x, s, c); }
+  static constexpr double cel_tol = 2e-7;        // error ~ tol^2 after the step
+};
+
+// sin(h) and 1 - cos(h) by their Taylor series through h^11 / h^12; relative
+// error below 1e-10 for |h| <= 0.5 and below 1e-19 for |h| <= 0.2.
+template <class T>
+PT_HD void sin_vers_small(T h, T* s, T* v) {
+  const T h2 = h * h;
+  T ps = T(-1.0 / 39916800.0);
+  ps = ps * h2 + T(1.0 / 362880.0);
+  ps = ps * h2 + T(-1.0 / 5040.0);
+  ps = ps * h2 + T(1.0 / 120.0);
+  ps = ps * h2 + T(-1.0 / 6.0);
+  *s = h + h * h2 * ps;
+  T pv = T(-1.0 / 479001600.0);
+  pv = pv * h2 + T(1.0 / 3628800.0);
+  pv = pv * h2 + T(-1.0 / 40320.0);
+  pv = pv * h2 + T(1.0 / 720.0);
+  pv = pv * h2 + T(-1.0 / 24.0);
+  *v = h2 * (T(0.5) + h2 * pv);
+}
+
+// (sin x, 1 - cos x) with full relative accuracy for every x.
+template <class T>
+PT_HD void sin_vers(T x, T* s, T* v) {
+  if (x > T(-Num<T>::rot_limit) && x < T(Num<T>::rot_limit)) {
+    sin_vers_small(x, s, v);
+  } else {
+    T sh, ch;
+    Num<T>::sincos(T(0.5) * x, &sh, &ch);
+    *s = T(2) * sh * ch;
+    *v = T(2) * sh * sh;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bulirsch's general complete elliptic integral
+//   cel(kc, p, a, b) = int_0^{pi/2} (a cos^2 t + b sin^2 t)
+//                      / ((cos^2 t + p sin^2 t) sqrt(cos^2 t + kc^2 sin^2 t)) dt
+// for p > 0 (Bulirsch 1969, Numer. Math. 13, 305).  Each Gauss transformation
+// keeps the integral's form, moves the modulus pair along the arithmetic-
+// geometric mean and updates (p, a, b); the result is read off once the mean
+// has converged.  Two integrals sharing kc are evaluated in one pass: the
+// mean is common, only (p, a, b) differ.  The caller passes sqrt(p), which it
+// can often form without cancellation.
+// ---------------------------------------------------------------------------
+template <class T> struct CelPair { T r1, r2; };
+
+template <class T, int FIXED_ITERS, class Op = Num<T>>
+PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T b1, T sp2, T a2, T b2) {
+  T mu = T(1), kk = kc, prod = kc;
+  T p1 = sp1, p2 = sp2;
+  b1 = b1 * Op::rcp(sp1);
+  b2 = b2 * Op::rcp(sp2);
+  // One Gauss step; returns false once the mean has converged.
+  auto step = [&](bool last) {
+    const T r1 = Op::rcp(p1), r2 = Op::rcp(p2);
+    const T g1 = prod * r1, g2 = prod * r2;
+    const T f1 = a1, f2 = a2;
+    a1 = a1 + b1 * r1;
+    a2 = a2 + b2 * r2;
+    b1 = T(2) * (b1 + f1 * g1);
+    b2 = T(2) * (b2 + f2 * g2);
+    p1 = g1 + p1;
+    p2 = g2 + p2;
+    const T mu_old = mu;
+    mu = mu + kk;
+    if (FIXED_ITERS == 0 && fabs(mu_old - kk) <= mu_old * T(Op::cel_tol)) return false;
+    if (last) return false;
+    kk = T(2) * Op::sqrt(prod);
+    prod = kk * mu;
+    return true;
+  };
+  if (FIXED_ITERS > 0) {
+#pragma unroll
+    for (int it = 0; it < (FIXED_ITERS > 0 ? FIXED_ITERS : 1); ++it) step(it == FIXED_ITERS - 1);
+  } else {
+    for (int it = 0; it < 40; ++it)
+      if (!step(false)) break;
+  }
+  const T hp = T(0.5 * kPi);
+  CelPair<T> r;
+  r.r1 = hp * (b1 + a1 * mu) * Op::rcp(mu * (mu + p1));
+  r.r2 = hp * (b2 + a2 * mu) * Op::rcp(mu * (mu + p2));
+  return r;
+}
+
+// Gauss steps the float path needs: the bulk path keeps kc >= 0.02, where
+// five steps bring the mean to float precision.
+constexpr int kCelItersF32 = 5;
+
+// ---------------------------------------------------------------------------
+// Orbit.  Per-light-curve constants are formed once in double precision; the
+// per-point work solves Kepler's equation in the frame of the inferior
+// conjunction (t0, true anomaly f_c = pi/2 - w), where near-transit quantities
+// are small and keep their relative precision in float.
+//
+// With E = E_c + x, Kepler's equation E - e sin E = M becomes
+//   x - e (cos E_c sin x - sin E_c (1 - cos x)) = dM,   dM = M - M_c,
+// and the sky position relative to the star, in units of a, is
+//   X = cos w (cos E - cos E_c) - sin w sqrt(1-e^2) (sin E - sin E_c)
+//   Y = r_c + sin w (cos E - cos E_c) + cos w sqrt(1-e^2) (sin E - sin E_c)
+// (X along the line of nodes, Y the in-plane direction towards the
+// observer), so that z = (a/R*) sqrt(X^2 + (Y cos i)^2) and the planet is in
+// front of the star when Y > 0.  The conjunction terms cancel exactly in X.
+// ---------------------------------------------------------------------------
+struct OrbitConst {
+  double t0, inv_p;       // phase = (t - t0) / P, in double
+  double aR, e, cos_i, sq1me2, cw, sw, cEc, sEc, rc, d1;
+  double dm_cut;          // |dM| beyond this: certainly out of transit
+  int32_t circular, valid;
+};
+
+// b is the transit impact parameter a cos i (1-e^2)/(1+e sin w) / R*; t0 the
+// time of inferior conjunction.  k_max bounds the radius ratios the orbit is
+// used with (for the out-of-transit cut; pass a negative value to disable).
+PT_HD OrbitConst orbit_const(double t0, double P, double aR, double b, double e,
+                             double w, double k_max) {
+  OrbitConst o;
+  o.t0 = t0;
+  o.inv_p = 1.0 / P;
+  o.aR = aR;
+  o.e = e;
+  o.valid = (P > 0.0 && aR > 0.0 && e >= 0.0 && e < 1.0 && b >= 0.0) ? 1 : 0;
+  o.cos_i = (b / aR) * (1.0 + e * ::sin(w)) / (1.0 - e * e);
+  if (!(o.cos_i <= 1.0)) o.valid = 0;
+  o.sq1me2 = ::sqrt(1.0 - e * e);
+  o.cw = ::cos(w);
+  o.sw = ::sin(w);
+  const double fc = 0.5 * kPi - w;
+  const double Ec = 2.0 * ::atan2(::sqrt(1.0 - e) * ::sin(0.5 * fc), ::sqrt(1.0 + e) * ::cos(0.5 * fc));
+  o.cEc = ::cos(Ec);
+  o.sEc = ::sin(Ec);
+  o.rc = 1.0 - e * o.cEc;
+  o.d1 = 1.0 - e * o.cEc;  // dM/dx at conjunction
+  o.circular = (e == 0.0) ? 1 : 0;
+  // Out-of-transit bound: in transit needs |f - f_c| < asin((1+k)/(aR(1-e)))
+  // (projected distance >= r |cos(w+f)| >= a(1-e)|sin(f-f_c)|, and the planet
+  // is behind the star beyond pi/2), and |dM| <= max(dM/df) |f - f_c| with
+  // max dM/df = (1+e)^1.5 / sqrt(1-e).
+  o.dm_cut = 4.0;  // no cut (|dM| <= pi)
+  if (k_max >= 0.0) {
+    const double s = (1.0 + k_max) / (aR * (1.0 - e));
+    if (s < 1.0) {
+      const double c = ::pow(1.0 + e, 1.5) / ::sqrt(1.0 - e) * ::asin(s);
+      o.dm_cut = c * (1.0 + 1e-6) + 1e-9;
+    }
+  }
+  return o;
+}
+
+// Mean-anomaly offset from conjunction, reduced to [-pi, pi], in double.
+PT_HD double mean_anomaly_offset(const OrbitConst& o, double t) {
+  const double ph = (t - o.t0) * o.inv_p;
+  return 2.0 * kPi * (ph - ::rint(ph));
+}
+
+// Signed z for a mean-anomaly offset dm (already in the working type).
+// OUT marks "certainly out of transit" (only when the cut is enabled).
+template <class T, bool CUT>
+PT_HD T orbit_z_from_dm(const OrbitConst& o, T dm, T big_out) {
+  if (CUT && fabs(dm) > T(o.dm_cut)) return big_out;
+  const T e = T(o.e);
+  T s, v;  // sin x, 1 - cos x
+  if (o.circular) {
+    sin_vers(dm, &s, &v);
+  } else {
+    const T cEc = T(o.cEc), sEc = T(o.sEc);
+    const T ec = e * cEc, es = e * sEc;
+    // |E - M| <= e brackets the root: x in dm - e sin E_c +- e.
+    const T lo = dm - es - e, hi = dm - es + e;
+    // Newton from x = 0 on the conjunction-frame equation; the trigonometric
+    // functions of x are carried along by exact rotations through each step,
+    // so near transit no sine or cosine is evaluated.
+    T x = T(0);
+    s = T(0);
+    v = T(0);
+    for (int it = 0; it < Num<T>::newton_max; ++it) {
+      const T g = x - (ec * s - es * v) - dm;
+      const T gp = T(1) - ec * (T(1) - v) + es * s;       // 1 - e cos(E_c + x)
+      T xn = x - g * Num<T>::rcp(gp);
+      xn = xn < lo ? lo : (xn > hi ? hi : xn);
+      const T dx = xn - x;
+      x = xn;
+      if (fabs(dx) < T(Num<T>::rot_limit)) {
+        T sd, vd;
+        sin_vers_small(dx, &sd, &vd);
+        const T s_new = s + sd - s * vd - v * sd;          // sin(x + dx)
+        const T v_new = v + vd - v * vd + s * sd;          // 1 - cos(x + dx)
+        s = s_new;
+        v = v_new;
+      } else {
+        sin_vers(x, &s, &v);
+      }
+      if (fabs(dx) <= Num<T>::newton_tol * fabs(x) + T(1e-30)) break;
+    }
+  }
+  const T dc = -(T(o.cEc) * v + T(o.sEc) * s);             // cos E - cos E_c
+  const T ds = T(o.cEc) * s - T(o.sEc) * v;                // sin E - sin E_c
+  const T sq = T(o.sq1me2);
+  const T X = T(o.cw) * dc - T(o.sw) * sq * ds;
+  const T Y = T(o.rc) + T(o.sw) * dc + T(o.cw) * sq * ds;
+  const T Yc = Y * T(o.cos_i);
+  const T z = T(o.aR) * Num<T>::sqrt(X * X + Yc * Yc);
+  return Y < T(0) ? -z : z;
+}
+
+// ---------------------------------------------------------------------------
+// Mandel & Agol quadratic model.  The three limb-darkening-factored functions
+// are returned as le = lambda_e, ld = lambda_d + 2/3 Theta(k - z), ed = eta_d;
+// with c = u1 + 2 u2 the flux is
+//   F = 1 - [(1-c) le + c ld + u2 ed] / (1 - u1/3 - u2/6).
+// ---------------------------------------------------------------------------
+template <class T> struct MaAlpha { T le, ld, ed; };
+
+// Shared elliptic part.  In the limb region (1-k < z < 1+k; the paper's case
+// with lambda_1) and inside the disc (z < 1-k, k < 1/2; lambda_2) the
+// elliptic combination is
+//   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)]
+// with kc = sqrt(1 - m) formed without cancellation.  C_K K + C_E E is one
+// cel with p = 1 and C_P Pi is one cel with p = 1 - n.
+template <class T, int ITERS, class Op = Num<T>>
+PT_HD T ma_elliptic(T z, T k, bool limb) {
+  const T zmk = z - k, zpk = z + k;
+  const T a = zmk * zmk, b = zpk * zpk;
+  const T q = (k - z) * (k + z);
+  const T z2 = z * z, k2 = k * k;
+  const T azmk = fabs(zmk);
+  T kc, ck, ce, sp, pref;
+  if (limb) {
+    const T bm1 = (zpk - T(1)) * (zpk + T(1));              // b - 1
+    kc = Op::sqrt(bm1 * Op::rcp(T(4) * z * k));
+    ck = (T(1) - b) * (T(2) * b + a - T(3)) - T(3) * q * (b - T(2));
+    ce = T(4) * z * k * (z2 + T(7) * k2 - T(4));
+    sp = Op::rcp(azmk);                                  // sqrt(1/a)
+    pref = T(1.0 / (9.0 * kPi)) * Op::rcp(Op::sqrt(k * z));
+  } else {
+    const T oma = (T(1) - zmk) * (T(1) + zmk);              // 1 - a
+    const T omb = (T(1) - zpk) * (T(1) + zpk);              // 1 - b
+    kc = Op::sqrt(omb * Op::rcp(oma));
+    ck = T(1) - T(5) * z2 + k2 + q * q;
+    ce = oma * (z2 + T(7) * k2 - T(4));
+    sp = zpk * Op::rcp(azmk);                            // sqrt(b/a)
+    pref = T(2.0 / (9.0 * kPi)) * Op::rcp(Op::sqrt(oma));
+  }
+  // C_P = -3 q / a; with b_Pi = C_P / sqrt(p) the ratio is exact:
+  // limb: -3q/a * |z-k| = 3 (z+k) sign(z-k);  inside: the same times 1/(z+k)
+  const T cp = T(-3) * q * Op::rcp(a);
+  const CelPair<T> r = cel2<T, ITERS, Op>(kc, T(1), ck + ce, ck + ce * kc * kc, sp, cp, cp);
+  return pref * (r.r1 + r.r2);
+}
+
+// lambda_e and eta_1 in the limb region, with the square root of
+// D = 4z^2 - (1+z^2-k^2)^2 = (z-(1-k))(1+k-z)(1+z-k)(1+z+k) formed as a
+// product and the two angles by atan2 (no acos near +-1).
+template <class T>
+PT_HD void ma_limb_terms(T z, T k, T* le, T* ed) {
+  const T k2 = k * k, z2 = z * z;
+  T D = (z - (T(1) - k)) * (T(1) + k - z) * (T(1) + z - k) * (T(1) + z + k);
+  D = D > T(0) ? D : T(0);
+  const T sD = Num<T>::sqrt(D);
+  const T kap0 = Num<T>::atan2(sD, k2 + z2 - T(1));
+  const T kap1 = Num<T>::atan2(sD, T(1) - k2 + z2);
+  *le = (k2 * kap0 + kap1 - T(0.5) * sD) * T(1.0 / kPi);
+  const T eta2 = T(0.5) * k2 * (k2 + T(2) * z2);
+  *ed = (kap1 + T(2) * eta2 * kap0 - T(0.25) * (T(1) + T(5) * k2 + z2) * sD) * T(0.5 / kPi);
+}
+
+// Float bulk: valid for k <= 1/2 away from the contact points; callers route
+// the rest to ma_alpha_exact.  z must satisfy 0 <= z < 1 + k.
+template <class T>
+PT_HD MaAlpha<T> ma_alpha_bulk(T z, T k) {
+  MaAlpha<T> r;
+  const bool limb = z > T(1) - k;
+  const T ell = ma_elliptic<T, kCelItersF32>(z, k, limb);
+  if (limb) {
+    ma_limb_terms(z, k, &r.le, &r.ed);
+    r.ld = ell;
+  } else {
+    const T k2 = k * k;
+    r.le = k2;
+    r.ed = T(0.5) * k2 * (k2 + T(2) * z * z);
+    r.ld = ell + (z < k ? T(2.0 / 3.0) : T(0));
+  }
+  return r;
+}
+
+// Fast-path bulk: z and the limb angles in float, the elliptic combination
+// (whose O(1) terms cancel to an O(k^2) result) in double through NumFast.
+// Valid for k <= 1/2, 0 <= z < 1 + k, away from z = k and z = 1 - k.
+PT_HD MaAlpha<float> ma_alpha_mixed(float zf, float kf, double k) {
+  MaAlpha<float> r;
+  const double z = zf;
+  const bool limb = z > 1.0 - k;
+  const double ell = ma_elliptic<double, 0, NumFast>(z, k, limb);
+  if (limb) {
+    ma_limb_terms<float>(zf, kf, &r.le, &r.ed);
+    r.ld = float(ell);
+  } else {
+    const double k2 = k * k;
+    r.le = float(k2);
+    r.ed = float(0.5 * k2 * (k2 + 2.0 * z * z));
+    r.ld = float(ell + (z < k ? 2.0 / 3.0 : 0.0));
+  }
+  return r;
+}
+
+// Complete elliptic integrals K(m), E(m) by cel (p = 1).
+template <class T>
+PT_HD void ellke(T m, T* K, T* E) {
+  const T kc = Num<T>::sqrt(T(1) - m);
+  const CelPair<T> r = cel2<T, 0>(kc, T(1), T(1), T(1), T(1), T(1), kc * kc);
+  *K = r.r1;
+  *E = r.r2;
+}
+
+// All cases of the Mandel & Agol table in the working type (double in
+// practice).  Equalities are taken after snapping |z-k| < 1e-9,
+// |z-(1-k)| < 1e-12 (k < 1/2), z < 1e-12 and |k-1/2| < 1e-12 onto them; for
+// k > 1/2 a distance within 1e-12 of 1-k is moved to 1-k+1e-12, where the
+// limb formula is still finite.
+template <class T>
+PT_HD MaAlpha<T> ma_alpha_exact(T z, T k) {
+  MaAlpha<T> r{T(0), T(0), T(0)};
+  if (!(z >= T(0))) return r;
+  if (fabs(k - T(0.5)) < T(1e-12)) k = T(0.5);
+  if (z < T(1e-12)) z = T(0);
+  if (fabs(z - k) < T(1e-9)) z = k;
+  if (z >= T(1) + k) return r;
+  if (fabs(z - (T(1) - k)) < T(1e-12)) {
+    if (k < T(0.5)) z = T(1) - k;
+    else if (k > T(0.5) && k < T(1)) z = T(1) - k + T(1e-12);
+  }
+  const T k2 = k * k, z2 = z * z;
+  const T third = T(1.0 / 3.0), tt = T(2.0 / 3.0);
+  if (k >= T(1) && z <= k - T(1)) {            // star fully covered
+    r.le = T(1); r.ld = tt; r.ed = T(0.5);
+    return r;
+  }
+  const T eta2 = T(0.5) * k2 * (k2 + T(2) * z2);
+  if (z == T(0)) {                              // centred (k < 1)
+    const T om = T(1) - k2;
+    r.le = k2;
+    r.ld = -tt * om * Num<T>::sqrt(om) + tt;
+    r.ed = eta2;
+    return r;
+  }
+  const bool limb = z > T(1) - k || (k > T(0.5) && z >= T(1) - k);
+  if (limb && z != k) {                         // partial overlap of the limb
+    ma_limb_terms(z, k, &r.le, &r.ed);
+    r.ld = ma_elliptic<T, 0>(z, k, true) + (z < k ? tt : T(0));
+    return r;
+  }
+  if (z == k) {
+    if (k < T(0.5)) {                           // lambda_4, eta_2
+      T K, E;
+      ellke(T(4) * k2, &K, &E);
+      r.le = k2;
+      r.ld = third + T(2.0 / (9.0 * kPi)) * (T(4) * (T(2) * k2 - T(1)) * E + (T(1) - T(4) * k2) * K);
+      r.ed = eta2;
+    } else if (k == T(0.5)) {
+      r.le = k2;
+      r.ld = third - T(4.0 / (9.0 * kPi));
+      r.ed = T(3.0 / 32.0);
+    } else {                                    // lambda_3, eta_1 (k > 1/2)
+      T K, E;
+      ellke(T(1) / (T(4) * k2), &K, &E);
+      ma_limb_terms(z, k, &r.le, &r.ed);
+      r.ld = third + T(16.0 / (9.0 * kPi)) * k * (T(2) * k2 - T(1)) * E
+             - (T(1) - T(4) * k2) * (T(3) - T(8) * k2) * T(1.0 / (9.0 * kPi)) * Num<T>::rcp(k) * K;
+    }
+    return r;
+  }
+  r.le = k2;
+  r.ed = eta2;
+  if (z == T(1) - k) {                          // lambda_5 (k < 1/2)
+    r.ld = T(2.0 / (3.0 * kPi)) * acos(T(1) - T(2) * k)
+           - T(4.0 / (9.0 * kPi)) * (T(3) + T(2) * k - T(8) * k2) * Num<T>::sqrt(k * (T(1) - k));
+    return r;
+  }
+  r.ld = ma_elliptic<T, 0>(z, k, false) + (z < k ? tt : T(0));   // lambda_2, eta_2
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Gimenez model.  With b = k/(1+k), c = z/(1+k), nu = (n+2)/2 and the per-band
+// table T[n][j] = b^2 A'_{n,j} [P_j^(nu,1)(2b-1)]^2 (standard Jacobi
+// polynomials; A' absorbs Kopal's normalisation of G_j), the moments are
+//   alpha_n = (1-c^2)^(nu+1) sum_{j<npol} T[n][j] P_j^(0,nu+1)(1-2c^2),
+// the sum taken by Clenshaw's backward recurrence with the three-term
+// coefficients P_{j+1} = (A_j x + B_j) P_j - C_j P_{j-1} (DLMF 18.9.1).
+// The band table and the shared recurrence coefficients are separate arrays.
+// ---------------------------------------------------------------------------
+// Three-term recurrence of the standard Jacobi polynomials (DLMF 18.9.1),
+// P_{m+1} = (A x + B) P_m - C P_{m-1}, with P_0 = 1, P_1 = ((al+be+2) x + al-be)/2.
+PT_HD void jacobi_coef(int m, double al, double be, double* A, double* B, double* C) {
+  if (m == 0) {
+    *A = 0.5 * (al + be + 2.0);
+    *B = 0.5 * (al - be);
+    *C = 0.0;
+    return;
+  }
+  const double s = 2.0 * m + al + be;
+  const double den = 2.0 * (m + 1) * (m + al + be + 1.0) * s;
+  *A = (s + 1.0) * (s + 2.0) * s / den;
+  *B = (s + 1.0) * (al * al - be * be) / den;
+  *C = 2.0 * (m + al) * (m + be) * (s + 2.0) / den;
+}
+
+// A'_{n,j} = (-1)^j (2j+nu+2) j! Gamma(nu+1) / (nu (j+1) Gamma(nu+j+1)),
+// nu = (n+2)/2: the paper's precomputed table A_{n,j} with Kopal's
+// normalisation of the Jacobi polynomials absorbed (k- and z-independent).
+PT_HD double gimenez_aprime(int n, int j) {
+  const double nu = 0.5 * (n + 2);
+  const double lg = ::lgamma(j + 1.0) + ::lgamma(nu + 1.0) - ::lgamma(nu + j + 1.0);
+  const double sg = (j & 1) ? -1.0 : 1.0;
+  return sg * (2.0 * j + nu + 2.0) / (nu * (j + 1.0)) * ::exp(lg);
+}
+
+// Per-band table T[n][j] = b^2 A'_{n,j} [P_j^(nu,1)(2b-1)]^2, b = k/(1+k),
+// for one n and j < npol (aprime_n = A'_{n,0..npol-1}).
+template <class T>
+PT_HD void gimenez_band_table_n(double k, int n, int npol, const double* aprime_n, T* out_n) {
+  const double bt = k / (1.0 + k);
+  const double x = 2.0 * bt - 1.0;
+  const double nu = 0.5 * (n + 2);
+  double pm1 = 0.0, p = 1.0;
+  for (int j = 0; j < npol; ++j) {
+    out_n[j] = T(bt * bt * aprime_n[j] * p * p);
+    double A, B, C;
+    jacobi_coef(j, nu, 1.0, &A, &B, &C);
+    const double pn = (A * x + B) * p - C * pm1;
+    pm1 = p;
+    p = pn;
+  }
+}
+
+// All n = 0..nldc, written as T[n * npol + j].
+template <class T>
+PT_HD void gimenez_band_table(double k, int nldc, int npol, const double* aprime, T* out) {
+  for (int n = 0; n <= nldc; ++n) gimenez_band_table_n<T>(k, n, npol, aprime + n * npol, out + n * npol);
+}
+
+// Shared Clenshaw coefficients for sum_j T_j P_j^(0,nu+1)(x): per (n, j)
+// {A_j, B_j, C_{j+1}} of the recurrence with al = 0, be = nu + 1.
+PT_HD void gimenez_rec_coef(int n, int j, double* A, double* B, double* Cn) {
+  const double be = 0.5 * (n + 2) + 1.0;
+  double C;
+  jacobi_coef(j, 0.0, be, A, B, &C);
+  double A1, B1;
+  jacobi_coef(j + 1, 0.0, be, &A1, &B1, Cn);
+}
+
+// (1 - c^2)^(nu+1) for nu = (n+2)/2
+template <class T>
+PT_HD T gimenez_power(T om, int n) {
+  T r = om * om;                                // nu + 1 = 2 at n = 0
+  for (int i = 0; i < n / 2; ++i) r *= om;
+  if (n & 1) r *= Num<T>::sqrt(om);
+  return r;
+}
+
+// alpha_n = (1-c^2)^(nu+1) sum_{j<npol} T[n][j] P_j^(0,nu+1)(1-2c^2) by
+// Clenshaw's backward recurrence; rec holds {A_j, B_j, C_{j+1}} per (n, j)
+// as rec[3 * (n * npol + j) + 0..2].  Returns 0 for c >= 1 (no overlap).
+template <class T>
+PT_HD void gimenez_alpha(T z, T inv1pk, int nldc, int npol, const T* tab, const T* rec, T* alpha) {
+  const T c = z * inv1pk;
+  const T om = T(1) - c * c;
+  const T x = T(1) - T(2) * c * c;
+  for (int n = 0; n <= nldc; ++n) {
+    if (!(om > T(0))) { alpha[n] = (om == om) ? T(0) : om; continue; }
+    const T* tn = tab + n * npol;
+    const T* rn = rec + 3 * n * npol;
+    T y1 = T(0), y2 = T(0);
+    for (int j = npol - 1; j >= 0; --j) {
+      const T y0 = tn[j] + (rn[3 * j] * x + rn[3 * j + 1]) * y1 - rn[3 * j + 2] * y2;
+      y2 = y1;
+      y1 = y0;
+    }
+    alpha[n] = gimenez_power(om, n) * y1;
+  }
+}
+
+}  // namespace pt
