@@ -52,8 +52,13 @@ typedef enum {
 } pt_prec;
 
 typedef enum {
-  PT_MODEL_MA_QUAD = 0,    /* quadratic Mandel & Agol; u rows are (u1, u2)        */
-  PT_MODEL_GIMENEZ = 1     /* Gimenez; u rows are the general-law u_1..u_nldc     */
+  PT_MODEL_MA_QUAD = 0,    /* quadratic Mandel & Agol; u rows are (u1, u2)                 */
+  PT_MODEL_GIMENEZ = 1,    /* Gimenez; u rows are the general-law u_1..u_nldc              */
+  PT_MODEL_MA_INTERP = 2,  /* quadratic Mandel & Agol with lambda_e, lambda_d, eta_d from  */
+                           /* bilinear tables (Sect. 2.2.3; pt_ma_table_set); float path  */
+  PT_MODEL_MA_KHAT = 3     /* quadratic Mandel & Agol evaluated at each light curve's mean */
+                           /* radius ratio khat, depth scaled by k_i^2/khat^2 per band     */
+                           /* (Sect. 3.5; an approximation); float path                    */
 } pt_model;
 
 /* Library version, e.g. "pthip 1.0 gfx950". */
@@ -106,6 +111,16 @@ pt_status pt_ma_quad(const double* z, int64_t n, double k, const double* u, int3
 pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int32_t nldc,
                      int32_t nb, int32_t npol, pt_prec prec, double* flux, void* stream);
 
+/* Builds the interpolation tables of PT_MODEL_MA_INTERP (Sect. 2.2.3): the
+ * three functions lambda_e, lambda_d + 2/3 Theta(k-z), eta_d from the exact
+ * double path on a uniform grid of nk radius ratios in [k_lo, k_hi] and nz
+ * distances in [0, 1 + k_hi]; evaluation is bilinear in (k, z).  Radius
+ * ratios outside [k_lo, k_hi] use the exact float path.  The table is
+ * library-owned (one per device) and ready when the call returns.
+ * Errors: PT_ERR_ARG unless 0 < k_lo < k_hi, nk >= 2, nz >= 2,
+ * nk * nz <= 2^24. */
+pt_status pt_ma_table_set(double k_lo, double k_hi, int32_t nk, int32_t nz, void* stream);
+
 /* A ragged batch of light curves: each has its own orbit, exposure times,
  * exposure time and supersampling factor, and its own passbands, each with
  * its own radius ratio and limb darkening (Sects. 1, 2.1.3, 2.2.2, 3.2).
@@ -150,6 +165,19 @@ typedef struct {
 pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec,
                       void* flux, void* stream);
 
+/* Gaussian log-likelihood of observed fluxes under the batch model, one value
+ * per light curve, without writing the model flux (the paper notes that
+ * moving the likelihood to the GPU removes the flux transfer, Sect. 3.4):
+ *   log L_i = -1/2 sum_j ((obs_j - F_j)/sigma_i)^2 - N_i ln sigma_i - N_i/2 ln 2 pi
+ * over the N_i = n_band_i * t_count_i points of light curve i.
+ *   obs      [n_flux] observed flux in pt_lc_batch's output layout and type
+ *            (float for PT_PREC_FP32/PT_PREC_SURROGATE, double for FP64), device
+ *   sigma    [n_lc] white-noise standard deviation per light curve (> 0), device
+ *   loglike  [n_lc] output, device, double; summed in a fixed order
+ * Errors: as pt_lc_batch; PT_ERR_ARG for NULL obs/sigma/loglike. */
+pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec,
+                        const void* obs, const double* sigma, double* loglike, void* stream);
+
 /* Times the launch-shape candidates of pt_lc_batch for this batch (tile size,
  * resident waves per CU) with HIP events on `stream`, keeps the fastest for
  * the batch's shape, and writes a JSON report into report[report_len] (may be
@@ -190,6 +218,14 @@ pt_status pt_mlp_forward(const pt_mlp* w, const float* zk, int64_t n, float* out
 pt_status pt_mlp_backward(const pt_mlp* w, const float* zk, const float* act, const float* dout,
                           int64_t n, pt_mlp* grad, void* stream);
 
+/* Weighted squared error of out[n][3] (network units alpha/k^2) against the
+ * exact alpha[n][3] of pt_mlp_datagen at the rows zk[n][2] (float), with
+ * weight (k/0.3)^4 + 1e-3 per row (the flux error is about k^2 times the
+ * output error); dout[n][3] receives dLoss/dout and loss[0] (device) the
+ * mean.  Runs on `stream`. */
+pt_status pt_mlp_loss_grad(const float* out, const float* zk, const double* alpha, int64_t n,
+                           float* dout, float* loss, void* stream);
+
 /* Adam update of all weights in place (m, v are first/second moments with
  * the same layout; step counts from 1). */
 pt_status pt_mlp_adam_step(pt_mlp* w, const pt_mlp* grad, pt_mlp* m, pt_mlp* v, int64_t step,
@@ -201,6 +237,15 @@ pt_status pt_mlp_adam_step(pt_mlp* w, const pt_mlp* grad, pt_mlp* m, pt_mlp* v, 
  * the exact functions. */
 pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, double k_hi,
                            void* stream);
+
+/* Fraction of trust-map cells (over c = z/(1+k) in [0,1), k in [k_lo, k_hi])
+ * in which the exact model accepted the installed network (-1 on error). */
+double pt_surrogate_trusted_fraction(void);
+
+/* Raw outputs (alpha/k^2 units) of the installed network on its bf16-MFMA
+ * inference path for float rows zk[n][2], out[n][3] float: no trust map and
+ * no fallback (for checking inference against pt_mlp_forward). */
+pt_status pt_mlp_infer(const float* zk, int64_t n, float* out, void* stream);
 
 /* Evaluates the installed surrogate's three functions at zk[n][2] (double),
  * out[n][3] (double), with the same fallback rules as the batch path. */

@@ -155,3 +155,80 @@ def surrogate_targets(zk):
     eta_d) at each (z, k) row; zero for z >= 1 + k."""
     zk = np.asarray(zk, np.float64)
     return ma_alpha_many(zk[:, 0], zk[:, 1])
+
+
+def loglike(batch, obs, sigma, model: int = 0, npol: int = 50, u=None, flux=None):
+    """Gaussian log-likelihood per light curve, written out from its
+    definition: -1/2 sum ((obs - F)/sigma)^2 - N ln sigma - N/2 ln(2 pi)."""
+    F = lc_batch(batch, model=model, npol=npol, u=u) if flux is None else flux
+    out = np.empty(len(batch["t_start"]))
+    for i in range(len(out)):
+        nb = batch["band_off"][i + 1] - batch["band_off"][i]
+        n = int(nb * batch["t_count"][i])
+        sl = slice(batch["flux_off"][i], batch["flux_off"][i] + n)
+        r = (np.asarray(obs[sl], np.float64) - F[sl]) / sigma[i]
+        out[i] = -0.5 * np.sum(r * r) - n * np.log(sigma[i]) - 0.5 * n * np.log(2 * np.pi)
+    return out
+
+
+# -- model variants of the paper, written out from their definitions ----------------------
+
+def ma_table(k_lo, k_hi, nk, nz):
+    """The three Mandel-Agol functions on a uniform grid of nk radius ratios in
+    [k_lo, k_hi] and nz distances in [0, 1 + k_hi] (Sect. 2.2.3)."""
+    ks = np.linspace(k_lo, k_hi, nk)
+    zs = np.linspace(0.0, 1.0 + k_hi, nz)
+    tab = np.zeros((nk, nz, 3))
+    for i, k in enumerate(ks):
+        tab[i] = ma_alpha_many(zs, np.full(nz, k))
+    return tab
+
+
+def ma_interp_alpha(z, k, tab, k_lo, k_hi):
+    """Bilinear interpolation of the table in (k, z); zero for z >= 1 + k or
+    z < 0; exact values for k outside [k_lo, k_hi]."""
+    nk, nz = tab.shape[:2]
+    if z < 0 or z >= 1 + k:
+        return np.zeros(3)
+    if not (k_lo <= k <= k_hi):
+        return ma_alpha(z, k)[0]
+    fk = (k - k_lo) / (k_hi - k_lo) * (nk - 1)
+    fz = z / (1 + k_hi) * (nz - 1)
+    ik = min(nk - 2, max(0, int(fk)))
+    iz = min(nz - 2, max(0, int(fz)))
+    wk, wz = fk - ik, fz - iz
+    return ((1 - wk) * (1 - wz) * tab[ik, iz] + (1 - wk) * wz * tab[ik, iz + 1]
+            + wk * (1 - wz) * tab[ik + 1, iz] + wk * wz * tab[ik + 1, iz + 1])
+
+
+def lc_batch_ma_variant(batch, variant, table=None, k_lo=None, k_hi=None):
+    """Supersampled quadratic Mandel-Agol batch with the three functions taken
+    (a) from the bilinear table ("interp", Sect. 2.2.3), or (b) at the light
+    curve's mean radius ratio khat with the depth of band i multiplied by
+    k_i^2 / khat^2 ("khat", Sect. 3.5).  Small batches only (Python loops)."""
+    flux = np.empty(batch["n_flux"])
+    for lc in range(len(batch["t_start"])):
+        s0, cnt, n = batch["t_start"][lc], batch["t_count"][lc], int(batch["nss"][lc])
+        b0, b1 = batch["band_off"][lc], batch["band_off"][lc + 1]
+        if b1 == b0 or cnt == 0:
+            continue
+        prm = tuple(batch[key][lc] for key in ("t0", "P", "aR", "b", "e", "w"))
+        t = batch["t"][s0:s0 + cnt]
+        ts = (t[:, None] + batch["t_exp"][lc] * ((np.arange(n) + 0.5) / n - 0.5)[None, :]).ravel()
+        z = orbit_z(ts, *prm)
+        khat = batch["k"][b0:b1].mean()
+        if variant == "khat":
+            al_hat = ma_alpha_many(np.where(z < 0, 2.0 + khat, z), np.full(len(z), khat))
+        for j, bnd in enumerate(range(b0, b1)):
+            k = batch["k"][bnd]
+            u1, u2 = batch["u"][bnd]
+            c = u1 + 2 * u2
+            w = np.array([1 - c, c, u2]) / (1 - u1 / 3 - u2 / 6)
+            if variant == "interp":
+                al = np.array([ma_interp_alpha(zz, k, table, k_lo, k_hi) for zz in z])
+                loss = al @ w
+            else:
+                loss = (al_hat @ w) * (k * k / (khat * khat))
+            off = batch["flux_off"][lc] + j * cnt
+            flux[off:off + cnt] = 1 - loss.reshape(cnt, n).mean(1)
+    return flux

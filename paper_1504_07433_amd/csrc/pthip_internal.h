@@ -30,8 +30,20 @@ struct TileDesc {
   int32_t pad;
 };
 
-enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2 };
-enum : int { kModelMA = 0, kModelGimenez = 1 };
+// kPrecSurrogateBf16: the surrogate with bf16-only products (no hi/lo split)
+enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2, kPrecSurrogateBf16 = 3 };
+// kModelMAInterp: bilinear lambda_e, lambda_d, eta_d tables (Sect. 2.2.3);
+// kModelMAKhat: the functions at the light curve's mean k, depth scaled by
+// k_i^2 / khat^2 per band (Sect. 3.5).
+enum : int { kModelMA = 0, kModelGimenez = 1, kModelMAInterp = 2, kModelMAKhat = 3 };
+
+// Interpolation table of the three Mandel-Agol functions on a uniform
+// (k, z) grid: k in [k_lo, k_hi] (nk nodes), z in [0, 1 + k_hi] (nz nodes).
+struct MaTable {
+  const float4* tab;    // [nk][nz] {lambda_e, lambda_d + 2/3 Theta, eta_d, 0}
+  float k_lo, k_hi, z_hi;
+  int32_t nk, nz;
+};
 
 // Subsamples whose z values a wave keeps in LDS at once.
 constexpr int kZChunk = 16;
@@ -71,6 +83,16 @@ struct BatchArgs {
   int32_t model;
   // surrogate
   const void* mlp;      // device MlpDev (bf16 weights) or null
+  // fused likelihood (obs == null: write flux)
+  const void* obs;      // observed flux, same layout and type as flux
+  const double* sigma;  // [n_lc] white-noise sigma
+  double* partial;      // [n_tiles] sum of squared normalised residuals
+  const int32_t* lc_tile_off;  // [n_lc+1] CSR of tiles per light curve
+  const int32_t* lc_tiles;
+  const int64_t* n_obs; // [n_lc] points per light curve (bands x exposures)
+  double* loglike;      // [n_lc]
+  MaTable matab;        // kModelMAInterp
+  double* khat;         // [n_lc] mean radius ratio (kModelMAKhat), written by prep
 };
 
 // Launchers (defined in pthip_kernels.hip).
@@ -87,5 +109,9 @@ hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u,
 // Prep (orbit and band constants, queue reset), Gimenez tables when needed,
 // and the persistent kernel on `workgroups` workgroups of kBlock threads.
 hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups, hipStream_t s);
+// Dynamic LDS of the batch kernel; opt-in of the surrogate variants above 64 KiB.
+size_t batch_lds_bytes(int prec, int model);
+hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab, hipStream_t s);
+hipError_t prepare_batch_kernels();
 
 }  // namespace pt

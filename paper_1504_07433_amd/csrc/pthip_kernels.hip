@@ -9,6 +9,7 @@
 //                    ragged batch (Sects. 2.1.3, 2.2.2, 3.2)
 #include <type_traits>
 
+#include "mlp_device.h"
 #include "pthip_internal.h"
 
 namespace pt {
@@ -236,6 +237,12 @@ __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
       double kmax = 0.0;
       for (int bnd = a.band_off[i]; bnd < a.band_off[i + 1]; ++bnd) kmax = fmax(kmax, a.k[bnd]);
       a.oc[i] = orbit_const(a.t0[i], a.P[i], a.aR[i], a.b[i], a.e[i], a.w[i], kmax);
+      if (a.khat) {
+        double ks = 0.0;
+        for (int bnd = a.band_off[i]; bnd < a.band_off[i + 1]; ++bnd) ks += a.k[bnd];
+        const int nb = a.band_off[i + 1] - a.band_off[i];
+        a.khat[i] = nb > 0 ? ks / nb : 0.0;
+      }
     }
     if (i < a.n_band) a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
   }
@@ -298,17 +305,114 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
   return loss;
 }
 
-template <int PREC, int MODEL>
+// Surrogate: lanes whose (z, k) fall in a trusted cell take the network's
+// functions, the others the float path; the network runs for the whole
+// wave (MFMA) whenever any lane needs it.
+template <int SPLIT>
+__device__ __forceinline__ float ma_loss_surrogate(float z, const BandConst* __restrict__ bc,
+                                                   const MlpDev* __restrict__ m, __bf16* act, int lane) {
+  const bool in = z >= 0.0f && z < bc->onepk;
+  const bool tr = in && mlp_trusted(m, z, bc->kf);
+  float loss = 0.0f;
+  if (__any(tr)) {
+    float y[3];
+    mlp_eval_wave<SPLIT>(m, z, bc->kf, act, lane, y);
+    if (tr) {
+      const float k2 = bc->kf * bc->kf;
+      loss = k2 * (bc->wf[0] * y[0] + bc->wf[1] * y[1] + bc->wf[2] * y[2]);
+    }
+  }
+  if (in && !tr) loss = ma_loss<float>(z, bc);
+  return loss;
+}
+
+// Bilinear interpolation of the three functions (Sect. 2.2.3); k outside the
+// table's range falls back to the float path.
+__device__ __forceinline__ float ma_loss_interp(float z, const BandConst* __restrict__ bc, const MaTable& t) {
+  if (z < 0.0f || z >= bc->onepk) return 0.0f;
+  const float k = bc->kf;
+  if (!(k >= t.k_lo && k <= t.k_hi)) return ma_loss<float>(z, bc);
+  const float fk = (k - t.k_lo) / (t.k_hi - t.k_lo) * (t.nk - 1);
+  const float fz = z / t.z_hi * (t.nz - 1);
+  const int ik = min(t.nk - 2, max(0, (int)fk));
+  const int iz = min(t.nz - 2, max(0, (int)fz));
+  const float wk = fk - ik, wz = fz - iz;
+  const float4 a = t.tab[ik * t.nz + iz], b = t.tab[ik * t.nz + iz + 1];
+  const float4 c = t.tab[(ik + 1) * t.nz + iz], d = t.tab[(ik + 1) * t.nz + iz + 1];
+  const float w00 = (1 - wk) * (1 - wz), w01 = (1 - wk) * wz, w10 = wk * (1 - wz), w11 = wk * wz;
+  const float le = w00 * a.x + w01 * b.x + w10 * c.x + w11 * d.x;
+  const float ld = w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y;
+  const float ed = w00 * a.z + w01 * b.z + w10 * c.z + w11 * d.z;
+  return bc->wf[0] * le + bc->wf[1] * ld + bc->wf[2] * ed;
+}
+
+// Table of the three functions from the exact double path.
+__global__ __launch_bounds__(256) void k_ma_table(double k_lo, double k_hi, int nk, int nz, float4* __restrict__ tab) {
+  const int64_t n = (int64_t)nk * nz, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const int ik = (int)(e / nz), iz = (int)(e % nz);
+    const double k = k_lo + (k_hi - k_lo) * ik / (nk - 1);
+    const double z = (1.0 + k_hi) * iz / (nz - 1);
+    MaAlpha<double> r{0.0, 0.0, 0.0};
+    if (z < 1.0 + k) r = ma_alpha_exact<double>(z, k);
+    tab[e] = make_float4(float(r.le), float(r.ld), float(r.ed), 0.0f);
+  }
+}
+
+hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_ma_table, dim3(grid_for((int64_t)nk * nz, 256)), dim3(256), 0, s, k_lo, k_hi, nk, nz, tab);
+  return hipGetLastError();
+}
+
+// Loss of band `bc` summed over the subsamples held in the wave's LDS slice.
+template <int PREC, int MODEL, class T>
+__device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
+                                          const BatchArgs& a, const T* __restrict__ tb, const T* __restrict__ grec,
+                                          __bf16* act) {
+  static_assert(MODEL != kModelMAKhat || sizeof(T) == 4, "khat runs in the float path");
+  constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
+  T acc = T(0);
+  if constexpr (MODEL == kModelMAInterp) {
+    for (int s = 0; s < ns; ++s) acc += ma_loss_interp(zb[s * kWave + lane], bc, a.matab);
+  } else if constexpr (MODEL == kModelMAKhat) {
+    // zb holds three planes of the functions at khat: [3][kZChunk][kWave]
+    for (int s = 0; s < ns; ++s)
+      acc += bc->wf[0] * zb[s * kWave + lane] + bc->wf[1] * zb[(kZChunk + s) * kWave + lane] +
+             bc->wf[2] * zb[(2 * kZChunk + s) * kWave + lane];
+  } else if (MODEL == kModelMA) {
+    if constexpr (SUR) {
+      const MlpDev* __restrict__ mlp = reinterpret_cast<const MlpDev*>(a.mlp);
+      for (int s = 0; s < ns; ++s)
+        acc += ma_loss_surrogate<PREC == kPrecSurrogate ? 1 : 0>(zb[s * kWave + lane], bc, mlp, act, lane);
+    } else {
+      for (int s = 0; s < ns; ++s) acc += ma_loss<T>(zb[s * kWave + lane], bc);
+    }
+  } else {
+    for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.nldc, a.npol, tb, grec);
+  }
+  return acc;
+}
+
+// LOGL = false: write the flux.  LOGL = true: accumulate the squared
+// normalised residuals against the observed flux instead and write one
+// partial sum per tile (summed per light curve by k_loglike_reduce).
+template <int PREC, int MODEL, bool LOGL>
 __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
   using T = typename std::conditional<PREC == kPrecFP64, double, float>::type;
+  constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   extern __shared__ unsigned char lds_raw[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  T* zb = reinterpret_cast<T*>(lds_raw) + wv * (kZChunk * kWave);
+  constexpr int planes = MODEL == kModelMAKhat ? 3 : 1;
+  T* zb = reinterpret_cast<T*>(lds_raw) + wv * (planes * kZChunk * kWave);
+  __bf16* act = SUR ? reinterpret_cast<__bf16*>(lds_raw + (kBlock / kWave) * kZChunk * kWave * sizeof(T)) +
+                          wv * (kMlpLdsPerWave / 2)
+                    : nullptr;
   const T far_out = T(1e30);
   const T* __restrict__ gtab = reinterpret_cast<const T*>(a.gtab);
   const T* __restrict__ grec = reinterpret_cast<const T*>(a.grec);
   T* __restrict__ flux = reinterpret_cast<T*>(a.flux);
+  const T* __restrict__ obs = reinterpret_cast<const T*>(a.obs);
   const int64_t tab_stride = (int64_t)(a.nldc + 1) * a.npol;
 
   for (;;) {
@@ -325,40 +429,125 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
     const double* __restrict__ tl = a.t + a.t_start[lc];
     const double texp = a.t_exp[lc];
     const double inv_nss = 1.0 / nss;
-    T* __restrict__ fl = flux + a.flux_off[lc];
+    const int64_t fo = a.flux_off[lc];
+    const double inv_sigma = LOGL ? 1.0 / a.sigma[lc] : 0.0;
+    const double khat = MODEL == kModelMAKhat ? a.khat[lc] : 0.0;
+    const float khat_f = float(khat), khat_onepk = float(1.0 + khat), khat_omk = float(1.0 - khat);
+    const float inv_khat2 = MODEL == kModelMAKhat ? float(1.0 / (khat * khat)) : 0.0f;
     const int e_end = td.e0 + td.ne;
+    double r2 = 0.0;
+
+    // z for subsamples s0 .. s0+ns-1 of this lane's exposure into LDS
+    auto orbit_chunk = [&](double tm, int s0, int ns) {
+      for (int s = 0; s < ns; ++s) {
+        const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
+        const double dm = mean_anomaly_offset(oc, ts);
+        T z = orbit_z_from_dm<T, true>(oc, T(dm), far_out);
+        if (!oc.valid) z = T(NAN);
+        if constexpr (MODEL == kModelMAKhat) {
+          // the functions once per point at the mean radius ratio, shared by the bands
+          MaAlpha<float> r{0.0f, 0.0f, 0.0f};
+          if (z != z) r = MaAlpha<float>{z, z, z};
+          else if (z >= 0.0f && z < khat_onepk) r = ma_alpha_fast(z, khat_f, khat, khat > 0.5, khat_omk);
+          zb[s * kWave + lane] = r.le;
+          zb[(kZChunk + s) * kWave + lane] = r.ld;
+          zb[(2 * kZChunk + s) * kWave + lane] = r.ed;
+        } else {
+          zb[s * kWave + lane] = z;
+        }
+      }
+    };
+    auto finish = [&](T acc, int bnd, int i, bool act_lane) {
+      if constexpr (MODEL == kModelMAKhat) acc *= T(a.bc[bnd].kf * a.bc[bnd].kf * inv_khat2);
+      const T f = T(1) - acc * T(inv_nss);
+      const int64_t idx = fo + (int64_t)(bnd - b0) * cnt + i;
+      if (LOGL) {
+        if (act_lane) {
+          const double r = ((double)obs[idx] - (double)f) * inv_sigma;
+          r2 += r * r;
+        }
+      } else if (act_lane) {
+        flux[idx] = f;
+      }
+    };
 
     for (int eb = td.e0; eb < e_end; eb += kWave) {
       const int i = eb + lane;
-      const bool act = i < e_end;
-      const double tm = tl[act ? i : td.e0];
-      for (int s0 = 0; s0 < nss; s0 += kZChunk) {
-        const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
-        for (int s = 0; s < ns; ++s) {
-          const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
-          const double dm = mean_anomaly_offset(oc, ts);
-          T z = orbit_z_from_dm<T, true>(oc, T(dm), far_out);
-          if (!oc.valid) z = T(NAN);
-          zb[s * kWave + lane] = z;
-        }
+      const bool act_lane = i < e_end;
+      const double tm = tl[act_lane ? i : td.e0];
+      if (nss <= kZChunk) {
+        // one orbit solve per (exposure, subsample), shared by every band
+        orbit_chunk(tm, 0, nss);
+        for (int bnd = b0; bnd < b1; ++bnd)
+          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, a.bc + bnd, a, gtab + bnd * tab_stride, grec, act),
+                 bnd, i, act_lane);
+      } else {
+        // more subsamples than one LDS chunk: the orbit is solved per band
         for (int bnd = b0; bnd < b1; ++bnd) {
-          const BandConst* bc = a.bc + bnd;
           T acc = T(0);
-          if (MODEL == kModelMA) {
-            for (int s = 0; s < ns; ++s) acc += ma_loss<T>(zb[s * kWave + lane], bc);
-          } else {
-            const T* tb = gtab + bnd * tab_stride;
-            for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.nldc, a.npol, tb, grec);
+          for (int s0 = 0; s0 < nss; s0 += kZChunk) {
+            const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
+            orbit_chunk(tm, s0, ns);
+            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, a.bc + bnd, a, gtab + bnd * tab_stride, grec, act);
           }
-          if (act) {
-            T* f = fl + (int64_t)(bnd - b0) * cnt + i;
-            T v = acc;
-            if (s0 > 0) v += *f;
-            *f = (s0 + ns >= nss) ? T(1) - v * T(inv_nss) : v;
-          }
+          finish(acc, bnd, i, act_lane);
         }
       }
     }
+    if (LOGL) {
+      for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off);
+      if (lane == 0) a.partial[tid] = r2;
+    }
+  }
+}
+
+// log L_i = -1/2 sum r^2 - N_i ln sigma_i - N_i/2 ln 2 pi, summing the tile
+// partials of light curve i in tile order (deterministic).
+__global__ void k_loglike_reduce(const double* __restrict__ partial, const int32_t* __restrict__ lc_tile_off,
+                                 const int32_t* __restrict__ lc_tiles, const double* __restrict__ sigma,
+                                 const int64_t* __restrict__ n_obs, int n_lc, double* __restrict__ loglike) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_lc) return;
+  double s = 0.0;
+  for (int j = lc_tile_off[i]; j < lc_tile_off[i + 1]; ++j) s += partial[lc_tiles[j]];
+  const double n = (double)n_obs[i];
+  loglike[i] = -0.5 * s - n * log(sigma[i]) - 0.5 * n * log(2.0 * kPi);
+}
+
+size_t batch_lds_bytes(int prec, int model) {
+  size_t z = (size_t)(kBlock / kWave) * kZChunk * kWave * (prec == kPrecFP64 ? 8 : 4) * (model == kModelMAKhat ? 3 : 1);
+  if (prec == kPrecSurrogate || prec == kPrecSurrogateBf16) z += (size_t)(kBlock / kWave) * kMlpLdsPerWave;
+  return z;
+}
+
+hipError_t prepare_batch_kernels() {
+  const int lds = (int)batch_lds_bytes(kPrecSurrogate, kModelMA);
+  const void* fns[4] = {(const void*)k_lc_batch<kPrecSurrogate, kModelMA, false>,
+                        (const void*)k_lc_batch<kPrecSurrogateBf16, kModelMA, false>,
+                        (const void*)k_lc_batch<kPrecSurrogate, kModelMA, true>,
+                        (const void*)k_lc_batch<kPrecSurrogateBf16, kModelMA, true>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <bool LOGL>
+static void launch_main(const BatchArgs& a, int prec, int model, dim3 grid, size_t lds, hipStream_t s) {
+  const dim3 block(kBlock);
+  if (prec == kPrecFP64) {
+    if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelMA, LOGL>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelGimenez, LOGL>), grid, block, lds, s, a);
+  } else if (prec == kPrecSurrogate) {
+    hipLaunchKernelGGL((k_lc_batch<kPrecSurrogate, kModelMA, LOGL>), grid, block, lds, s, a);
+  } else if (prec == kPrecSurrogateBf16) {
+    hipLaunchKernelGGL((k_lc_batch<kPrecSurrogateBf16, kModelMA, LOGL>), grid, block, lds, s, a);
+  } else {
+    if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMA, LOGL>), grid, block, lds, s, a);
+    else if (model == kModelMAInterp) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMAInterp, LOGL>), grid, block, lds, s, a);
+    else if (model == kModelMAKhat) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMAKhat, LOGL>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelGimenez, LOGL>), grid, block, lds, s, a);
   }
 }
 
@@ -371,17 +560,19 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
     err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gaprime, a.gtab, prec, s);
     if (err != hipSuccess) return err;
   }
-  if (a.n_tiles == 0) return hipSuccess;
-  const size_t lds = (size_t)(kBlock / kWave) * kZChunk * kWave * (prec == kPrecFP64 ? 8 : 4);
-  const dim3 grid(workgroups), block(kBlock);
-  if (prec == kPrecFP64) {
-    if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelMA>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelGimenez>), grid, block, lds, s, a);
-  } else {
-    if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMA>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelGimenez>), grid, block, lds, s, a);
+  if (a.n_tiles > 0) {
+    const size_t lds = batch_lds_bytes(prec, model);
+    if (a.obs) launch_main<true>(a, prec, model, dim3(workgroups), lds, s);
+    else launch_main<false>(a, prec, model, dim3(workgroups), lds, s);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
   }
-  return hipGetLastError();
+  if (a.obs) {
+    hipLaunchKernelGGL(k_loglike_reduce, dim3((a.n_lc + 255) / 256), dim3(256), 0, s, a.partial, a.lc_tile_off,
+                       a.lc_tiles, a.sigma, a.n_obs, a.n_lc, a.loglike);
+    err = hipGetLastError();
+  }
+  return err;
 }
 
 }  // namespace pt

@@ -1,19 +1,595 @@
-// pthip_mlp.hip -- learned surrogate of the Mandel-Agol functions.
+// pthip_mlp.hip -- learned surrogate of the three Mandel-Agol functions:
+// exact training targets, float training kernels (forward, backward, Adam),
+// the bf16-MFMA inference network, and the trust map the exact model builds
+// for it.
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "../../include/pthip.h"
+#include "mlp_device.h"
 #include "pthip_internal.h"
+
+namespace pt {
+
+pt_status set_error(pt_status st, const char* fmt, ...);   // pthip_runtime.cpp
+
+#define MLP_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return set_error(PT_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+static int grid1(int64_t n, int block = 256) {
+  int64_t g = (n + block - 1) / block;
+  return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+// ---------------------------------------------------------------------------
+// Exact targets: (lambda_e, lambda_d + 2/3 Theta, eta_d) in double.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_datagen(const double* __restrict__ zk, int64_t n,
+                                                     double* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double z = zk[2 * i], k = zk[2 * i + 1];
+    MaAlpha<double> a{0.0, 0.0, 0.0};
+    if (z >= 0.0 && z < 1.0 + k) a = ma_alpha_exact<double>(z, k);
+    out[3 * i] = a.le;
+    out[3 * i + 1] = a.ld;
+    out[3 * i + 2] = a.ed;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Float training kernels.
+// C[M][N] (+)= sum_k A(i,k) B(k,j), A(i,k) = A[i*sa_i + k*sa_k],
+// B(k,j) = B[k*sb_k + j*sb_j]; blockIdx.z splits K into gridDim.z slices
+// written to C + z * M * N (summed by k_sum_slices).  64x64 tiles, 16-deep.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int64_t K, const float* __restrict__ A,
+                                              int64_t sa_i, int64_t sa_k, const float* __restrict__ B,
+                                              int64_t sb_k, int64_t sb_j, float* __restrict__ C) {
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int64_t kslice = (K + gridDim.z - 1) / gridDim.z;
+  const int64_t kb = blockIdx.z * kslice;
+  const int64_t ke = kb + kslice < K ? kb + kslice : K;
+  float acc[4][4] = {};
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int kk = e / 64, r = e % 64;
+      const int64_t k = k0 + kk;
+      const int i = i0 + r, j = j0 + r;
+      As[kk][r] = (k < ke && i < M) ? A[i * sa_i + k * sa_k] : 0.0f;
+      Bs[kk][r] = (k < ke && j < N) ? B[k * sb_k + j * sb_j] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ty * 4 + u]; b[u] = Bs[kk][tx * 4 + u]; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
+  }
+  float* Cz = C + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+      if (i < M && j < N) Cz[(int64_t)i * N + j] = acc[u][v];
+    }
+}
+
+__global__ void k_sum_slices(int64_t mn, int slices, const float* __restrict__ part, float* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mn; i += stride) {
+    float s = 0.0f;
+    for (int z = 0; z < slices; ++z) s += part[z * mn + i];
+    out[i] = s;
+  }
+}
+
+static hipError_t gemm(int M, int N, int64_t K, const float* A, int64_t sa_i, int64_t sa_k, const float* B,
+                       int64_t sb_k, int64_t sb_j, float* C, float* part, int slices, hipStream_t s) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64, slices);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, A, sa_i, sa_k, B, sb_k, sb_j,
+                     slices > 1 ? part : C);
+  if (slices > 1)
+    hipLaunchKernelGGL(k_sum_slices, dim3(grid1((int64_t)M * N)), dim3(256), 0, s, (int64_t)M * N, slices,
+                       part, C);
+  return hipGetLastError();
+}
+
+// features x = (2 z/(1+k) - 1, (k - k0)/ks)
+__global__ void k_features(const float* __restrict__ zk, int64_t n, float* __restrict__ x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float z = zk[2 * i], k = zk[2 * i + 1];
+    x[2 * i] = 2.0f * z / (1.0f + k) - 1.0f;
+    x[2 * i + 1] = (k - kFeatK0) * kFeatKS;
+  }
+}
+
+// pre = C + b (stored in the activation cache), h = silu(pre)
+__global__ void k_bias_silu(int64_t n, int width, const float* __restrict__ C, const float* __restrict__ b,
+                            float* __restrict__ pre, int64_t pre_stride, float* __restrict__ h) {
+  const int64_t total = n * width, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / width;
+    const int j = (int)(e % width);
+    const float p = C[e] + b[j];
+    if (pre) pre[i * pre_stride + j] = p;
+    if (h) h[e] = p / (1.0f + expf(-p));
+  }
+}
+
+__global__ void k_bias(int64_t n, int width, float* __restrict__ C, const float* __restrict__ b) {
+  const int64_t total = n * width, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride)
+    C[e] += b[e % width];
+}
+
+// h = silu(pre) from the cache
+__global__ void k_silu_from(int64_t n, const float* __restrict__ pre, int64_t pre_stride, float* __restrict__ h) {
+  const int64_t total = n * kH, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const float p = pre[(e / kH) * pre_stride + e % kH];
+    h[e] = p / (1.0f + expf(-p));
+  }
+}
+
+// g *= silu'(pre), silu'(p) = s (1 + p (1 - s)), s = sigmoid(p)
+__global__ void k_silu_back(int64_t n, const float* __restrict__ pre, int64_t pre_stride, float* __restrict__ g) {
+  const int64_t total = n * kH, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const float p = pre[(e / kH) * pre_stride + e % kH];
+    const float sg = 1.0f / (1.0f + expf(-p));
+    g[e] *= sg * (1.0f + p * (1.0f - sg));
+  }
+}
+
+// column sums of g [n][width] -> out [width] (deterministic: one block per column)
+__global__ void k_colsum(int64_t n, int width, const float* __restrict__ g, float* __restrict__ out) {
+  __shared__ float red[256];
+  const int j = blockIdx.x;
+  float s = 0.0f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += g[i * width + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// Weighted squared error in the network's units y = alpha / k^2, with weight
+// ((k/0.3)^4 + 1e-3): the flux error is about k^2 |dy|, so large k needs the
+// small relative error.  dout = dLoss/dy of the mean; per-block partial sums.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ zk,
+                                             const double* __restrict__ alpha, int64_t n,
+                                             float* __restrict__ dout, float* __restrict__ part) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float k = zk[2 * i + 1];
+    const double k2 = (double)k * k;
+    const float kk = k / 0.3f;
+    const float w = kk * kk * kk * kk + 1e-3f;
+    for (int c = 0; c < 3; ++c) {
+      const float t = (float)(alpha[3 * i + c] / k2);
+      const float d = y[3 * i + c] - t;
+      s += w * d * d / (float)(3 * n);
+      dout[3 * i + c] = 2.0f * w * d / (float)(3 * n);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference
+// ---------------------------------------------------------------------------
+__global__ void k_mlp_pack(const pt_mlp w, MlpDev* __restrict__ m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kH * kH; i += stride) {
+    const float a = w.W2[i], b = w.W3[i];
+    const __bf16 ah = (__bf16)a, bh = (__bf16)b;
+    m->W2hi[i] = ah; m->W2lo[i] = (__bf16)(a - (float)ah);
+    m->W3hi[i] = bh; m->W3lo[i] = (__bf16)(b - (float)bh);
+    if (i < 2 * kH) m->W1[i] = w.W1[i];
+    if (i < kH) { m->b1[i] = w.b1[i]; m->b2[i] = w.b2[i]; m->b3[i] = w.b3[i]; }
+    if (i < 3 * kH) m->W4[i] = w.W4[i];
+    if (i < 3) m->b4[i] = w.b4[i];
+  }
+}
+
+// Trust map: one wave per cell, 64 points on an 8 x 8 grid inside it (cell
+// edges included); the cell is trusted when the bound on the flux error,
+// 2|d lambda_e| + 4|d lambda_d| + 2|d eta_d| (the largest limb-darkening
+// weights of the quadratic law with coefficients from uniform (q1, q2)), is
+// below tol at every grid point.
+template <int SPLIT>
+__global__ __launch_bounds__(256) void k_mlp_trust(const MlpDev* __restrict__ m, float tol,
+                                                   uint8_t* __restrict__ cells) {
+  extern __shared__ unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __bf16* act = reinterpret_cast<__bf16*>(lds_raw) + wv * (kMlpLdsPerWave / 2);
+  const int cell = blockIdx.x * 4 + wv;
+  if (cell >= kTrustNC * kTrustNK) return;          // wave-uniform
+  const int ci = cell % kTrustNC, cj = cell / kTrustNC;
+  const float dk = (m->k_hi - m->k_lo) / kTrustNK;
+  const float c = (ci + (lane % 8) / 7.0f) / kTrustNC;
+  const float k = m->k_lo + dk * (cj + (lane / 8) / 7.0f);
+  const float z = fminf(c, 0.9999999f) * (1.0f + k);
+  float y[3];
+  mlp_eval_wave<SPLIT>(m, z, k, act, lane, y);
+  const MaAlpha<double> ex = ma_alpha_exact<double>((double)z, (double)k);
+  const double k2 = (double)k * k;
+  const bool band = fabsf(z - (1.0f - k)) < m->band || fabsf(z - (1.0f + k)) < m->band;
+  float e = (float)(2.0 * fabs(k2 * y[0] - ex.le) + 4.0 * fabs(k2 * y[1] - ex.ld) + 2.0 * fabs(k2 * y[2] - ex.ed));
+  if (band) e = 0.0f;                               // served exactly anyway
+  if (!(e <= tol)) e = 1e30f;
+  for (int off = 32; off > 0; off >>= 1) e = fmaxf(e, __shfl_xor(e, off));
+  if (lane == 0) cells[cell] = e <= tol ? 1 : 0;
+}
+
+__global__ void k_pack_trust(const uint8_t* __restrict__ cells, MlpDev* __restrict__ m) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= kTrustNC * kTrustNK / 32) return;
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) bits |= (uint32_t)(cells[w * 32 + b] & 1) << b;
+  m->trust[w] = bits;
+}
+
+__global__ void k_set_params(MlpDev* m, float band, float k_lo, float k_hi, int split) {
+  m->band = band; m->k_lo = k_lo; m->k_hi = k_hi; m->split = split;
+}
+
+// Surrogate values at (z, k) rows, with the exact fallback: out = alpha.
+template <int SPLIT>
+__global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev* __restrict__ m, const double* __restrict__ zk,
+                                                  int64_t n, double* __restrict__ out) {
+  extern __shared__ unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __bf16* act = reinterpret_cast<__bf16*>(lds_raw) + wv * (kMlpLdsPerWave / 2);
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 64; base < n; base += waves * 64) {
+    const int64_t i = base + lane;
+    const bool act_lane = i < n;
+    const double zd = act_lane ? zk[2 * i] : 0.5, kd = act_lane ? zk[2 * i + 1] : 0.1;
+    const float z = (float)zd, k = (float)kd;
+    const bool in = z >= 0.0f && z < 1.0f + k;
+    const bool tr = in && mlp_trusted(m, z, k);
+    float y[3] = {0, 0, 0};
+    if (__any(tr)) mlp_eval_wave<SPLIT>(m, z, k, act, lane, y);   // wave-uniform
+    double a0 = 0, a1 = 0, a2 = 0;
+    if (tr) {
+      const double k2 = (double)k * k;
+      a0 = k2 * y[0]; a1 = k2 * y[1]; a2 = k2 * y[2];
+    } else if (in) {
+      const MaAlpha<double> ex = ma_alpha_exact<double>(zd, kd);
+      a0 = ex.le; a1 = ex.ld; a2 = ex.ed;
+    }
+    if (act_lane) {
+      out[3 * i] = a0; out[3 * i + 1] = a1; out[3 * i + 2] = a2;
+    }
+  }
+}
+
+// Raw network outputs on the MFMA path (no trust map, no fallback).
+template <int SPLIT>
+__global__ __launch_bounds__(256) void k_mlp_infer(const MlpDev* __restrict__ m, const float* __restrict__ zk,
+                                                   int64_t n, float* __restrict__ out) {
+  extern __shared__ unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __bf16* act = reinterpret_cast<__bf16*>(lds_raw) + wv * (kMlpLdsPerWave / 2);
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 64; base < n; base += waves * 64) {
+    const int64_t i = base + lane;
+    const bool ok = i < n;
+    const float z = ok ? zk[2 * i] : 0.5f, k = ok ? zk[2 * i + 1] : 0.1f;
+    float y[3];
+    mlp_eval_wave<SPLIT>(m, z, k, act, lane, y);
+    if (ok) { out[3 * i] = y[0]; out[3 * i + 1] = y[1]; out[3 * i + 2] = y[2]; }
+  }
+}
+
+// Library-owned surrogate state for one device.
+struct SurrogateState {
+  MlpDev* dev_ptr = nullptr;
+  int dev = -1;
+  bool ready = false;
+  float band = 1e-3f, k_lo = 0.01f, k_hi = 0.3f;
+  int split = 1;
+  double trusted_fraction = 0.0;
+};
+static std::mutex g_mlp_mu;
+static SurrogateState g_sur[16];
+
+const MlpDev* surrogate_device_ptr(int dev) {
+  if (dev < 0 || dev >= 16 || !g_sur[dev].ready) return nullptr;
+  return g_sur[dev].dev_ptr;
+}
+
+int surrogate_split(int dev) { return (dev >= 0 && dev < 16) ? g_sur[dev].split : 1; }
+
+void surrogate_release() {
+  std::lock_guard<std::mutex> lk(g_mlp_mu);
+  for (int d = 0; d < 16; ++d) {
+    if (g_sur[d].dev_ptr) {
+      int cur = 0;
+      hipGetDevice(&cur);
+      hipSetDevice(d);
+      hipFree(g_sur[d].dev_ptr);
+      hipSetDevice(cur);
+    }
+    g_sur[d] = SurrogateState();
+  }
+}
+
+double surrogate_trusted_fraction(int dev) { return (dev >= 0 && dev < 16) ? g_sur[dev].trusted_fraction : 0.0; }
+
+static bool mlp_ok(const pt_mlp* w) {
+  return w && w->W1 && w->b1 && w->W2 && w->b2 && w->W3 && w->b3 && w->W4 && w->b4;
+}
+
+}  // namespace pt
+
+using namespace pt;
 
 extern "C" {
 
-static pt_status unsupported() { return PT_ERR_UNSUPPORTED; }
+pt_status pt_mlp_datagen(const double* zk, int64_t n, double* target, void* stream) {
+  if (n < 0) return set_error(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!zk || !target)) return set_error(PT_ERR_ARG, "zk or target is NULL");
+  if (n == 0) return PT_OK;
+  hipLaunchKernelGGL(k_mlp_datagen, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, zk, n, target);
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
+}
 
-pt_status pt_mlp_datagen(const double*, int64_t, double*, void*) { return unsupported(); }
-pt_status pt_mlp_forward(const pt_mlp*, const float*, int64_t, float*, float*, void*) { return unsupported(); }
-pt_status pt_mlp_backward(const pt_mlp*, const float*, const float*, const float*, int64_t, pt_mlp*, void*) {
-  return unsupported();
+// Forward in float.  act: [n][3][128] pre-activations (may be NULL).
+pt_status pt_mlp_forward(const pt_mlp* w, const float* zk, int64_t n, float* out, float* act, void* stream) {
+  if (!mlp_ok(w)) return set_error(PT_ERR_ARG, "weights incomplete");
+  if (n < 0) return set_error(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!zk || !out)) return set_error(PT_ERR_ARG, "zk or out is NULL");
+  if (n > (1LL << 26)) return set_error(PT_ERR_ARG, "n = %lld above 2^26 rows per call", (long long)n);
+  if (n == 0) return PT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  float *x = nullptr, *c = nullptr, *h = nullptr;
+  MLP_HIP(hipMallocAsync((void**)&x, n * 2 * sizeof(float), s));
+  MLP_HIP(hipMallocAsync((void**)&c, n * kH * sizeof(float), s));
+  MLP_HIP(hipMallocAsync((void**)&h, n * kH * sizeof(float), s));
+  hipLaunchKernelGGL(k_features, dim3(grid1(n)), dim3(256), 0, s, zk, n, x);
+  const float* Ws[3] = {w->W1, w->W2, w->W3};
+  const float* bs[3] = {w->b1, w->b2, w->b3};
+  const float* in = x;
+  int in_w = 2;
+  hipError_t err = hipSuccess;
+  for (int l = 0; l < 3 && err == hipSuccess; ++l) {
+    // c = in . W^T : A(i,k) = in[i*in_w + k], B(k,j) = W[j*in_w + k]; then
+    // h = silu(c + b) (the stream orders the GEMM's reads of h before the write)
+    err = gemm((int)n, kH, in_w, in, in_w, 1, Ws[l], 1, in_w, c, nullptr, 1, s);
+    hipLaunchKernelGGL(k_bias_silu, dim3(grid1(n * kH)), dim3(256), 0, s, n, kH, c, bs[l],
+                       act ? act + l * kH : nullptr, (int64_t)3 * kH, h);
+    in = h;
+    in_w = kH;
+  }
+  if (err == hipSuccess) {
+    err = gemm((int)n, 3, kH, in, kH, 1, w->W4, 1, kH, out, nullptr, 1, s);
+    hipLaunchKernelGGL(k_bias, dim3(grid1(n * 3)), dim3(256), 0, s, n, 3, out, w->b4);
+  }
+  hipFreeAsync(x, s);
+  hipFreeAsync(c, s);
+  hipFreeAsync(h, s);
+  if (err != hipSuccess) return set_error(PT_ERR_HIP, "mlp forward: %s", hipGetErrorString(err));
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
 }
-pt_status pt_mlp_adam_step(pt_mlp*, const pt_mlp*, pt_mlp*, pt_mlp*, int64_t, float, float, float, float, void*) {
-  return unsupported();
+
+pt_status pt_mlp_backward(const pt_mlp* w, const float* zk, const float* act, const float* dout, int64_t n,
+                          pt_mlp* grad, void* stream) {
+  if (!mlp_ok(w) || !mlp_ok(grad)) return set_error(PT_ERR_ARG, "weights or gradients incomplete");
+  if (n <= 0) return set_error(PT_ERR_ARG, "n = %lld must be > 0", (long long)n);
+  if (!zk || !act || !dout) return set_error(PT_ERR_ARG, "zk, act or dout is NULL");
+  if (n > (1LL << 26)) return set_error(PT_ERR_ARG, "n = %lld above 2^26 rows per call", (long long)n);
+  hipStream_t s = (hipStream_t)stream;
+  const int slices = (int)std::min<int64_t>(64, std::max<int64_t>(1, n / 4096));
+  float *x = nullptr, *h = nullptr, *g = nullptr, *g2 = nullptr, *part = nullptr;
+  MLP_HIP(hipMallocAsync((void**)&x, n * 2 * sizeof(float), s));
+  MLP_HIP(hipMallocAsync((void**)&h, n * kH * sizeof(float), s));
+  MLP_HIP(hipMallocAsync((void**)&g, n * kH * sizeof(float), s));
+  MLP_HIP(hipMallocAsync((void**)&g2, n * kH * sizeof(float), s));
+  MLP_HIP(hipMallocAsync((void**)&part, (size_t)slices * kH * kH * sizeof(float), s));
+  hipLaunchKernelGGL(k_features, dim3(grid1(n)), dim3(256), 0, s, zk, n, x);
+  const int64_t ps = 3 * kH;
+  hipError_t err = hipSuccess;
+  // output layer: dW4 = dout^T h3, db4 = sum dout, g = dout W4
+  hipLaunchKernelGGL(k_silu_from, dim3(grid1(n * kH)), dim3(256), 0, s, n, act + 2 * kH, ps, h);
+  err = gemm(3, kH, n, dout, 1, 3, h, kH, 1, grad->W4, part, slices, s);
+  hipLaunchKernelGGL(k_colsum, dim3(3), dim3(256), 0, s, n, 3, dout, grad->b4);
+  if (err == hipSuccess) err = gemm((int)n, kH, 3, dout, 3, 1, w->W4, kH, 1, g, nullptr, 1, s);
+  const float* Ws[3] = {w->W1, w->W2, w->W3};
+  float* gW[3] = {grad->W1, grad->W2, grad->W3};
+  float* gb[3] = {grad->b1, grad->b2, grad->b3};
+  for (int l = 2; l >= 0 && err == hipSuccess; --l) {
+    hipLaunchKernelGGL(k_silu_back, dim3(grid1(n * kH)), dim3(256), 0, s, n, act + l * kH, ps, g);
+    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, s, n, kH, g, gb[l]);
+    const int in_w = l == 0 ? 2 : kH;
+    const float* in = x;
+    if (l > 0) {
+      hipLaunchKernelGGL(k_silu_from, dim3(grid1(n * kH)), dim3(256), 0, s, n, act + (l - 1) * kH, ps, h);
+      in = h;
+    }
+    // dW = g^T in : A(i,k) = g[k*kH + i], B(k,j) = in[k*in_w + j]
+    err = gemm(kH, in_w, n, g, 1, kH, in, in_w, 1, gW[l], part, slices, s);
+    if (l > 0 && err == hipSuccess) {
+      // g_prev = g W : A(i,k) = g[i*kH + k], B(k,j) = W[k*in_w + j]
+      err = gemm((int)n, kH, kH, g, kH, 1, Ws[l], in_w, 1, g2, nullptr, 1, s);
+      float* t = g; g = g2; g2 = t;
+    }
+  }
+  hipFreeAsync(x, s);
+  hipFreeAsync(h, s);
+  hipFreeAsync(g, s);
+  hipFreeAsync(g2, s);
+  hipFreeAsync(part, s);
+  if (err != hipSuccess) return set_error(PT_ERR_HIP, "mlp backward: %s", hipGetErrorString(err));
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
 }
-pt_status pt_surrogate_set(const pt_mlp*, double, double, double, void*) { return unsupported(); }
-pt_status pt_surrogate_eval(const double*, int64_t, double*, void*) { return unsupported(); }
+
+// Weighted squared error of out against exact alpha (see k_mse) and its
+// gradient; loss (device, 1 float) receives the mean.
+pt_status pt_mlp_loss_grad(const float* out, const float* zk, const double* alpha, int64_t n, float* dout,
+                           float* loss, void* stream) {
+  if (n <= 0 || !out || !zk || !alpha || !dout || !loss) return set_error(PT_ERR_ARG, "bad loss arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks = std::min<int64_t>(1024, (n + 255) / 256);
+  float* part = nullptr;
+  MLP_HIP(hipMallocAsync((void**)&part, blocks * sizeof(float), s));
+  hipLaunchKernelGGL(k_mse, dim3(blocks), dim3(256), 0, s, out, zk, alpha, n, dout, part);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, (int64_t)blocks, 1, part, loss);
+  hipFreeAsync(part, s);
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
 }
+
+pt_status pt_mlp_adam_step(pt_mlp* w, const pt_mlp* grad, pt_mlp* m, pt_mlp* v, int64_t step, float lr, float beta1,
+                           float beta2, float eps, void* stream) {
+  if (!mlp_ok(w) || !mlp_ok(grad) || !mlp_ok(m) || !mlp_ok(v)) return set_error(PT_ERR_ARG, "incomplete parameter set");
+  if (step < 1) return set_error(PT_ERR_ARG, "step counts from 1");
+  hipStream_t s = (hipStream_t)stream;
+  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+  float** W[4] = {(float**)w, (float**)grad, (float**)m, (float**)v};
+  const int64_t sizes[8] = {2 * kH, kH, kH * kH, kH, kH * kH, kH, 3 * kH, 3};
+  for (int a = 0; a < 8; ++a)
+    hipLaunchKernelGGL(k_adam, dim3(grid1(sizes[a])), dim3(256), 0, s, sizes[a], W[0][a], (const float*)W[1][a],
+                       W[2][a], W[3][a], lr, beta1, beta2, eps, c1, c2);
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
+}
+
+pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, double k_hi, void* stream) {
+  if (!mlp_ok(w)) return set_error(PT_ERR_ARG, "weights incomplete");
+  if (!(fallback_band >= 0.0) || !(k_lo > 0.0) || !(k_hi > k_lo))
+    return set_error(PT_ERR_ARG, "need fallback_band >= 0 and 0 < k_lo < k_hi");
+  int dev = 0;
+  MLP_HIP(hipGetDevice(&dev));
+  if (dev >= 16) return set_error(PT_ERR_UNSUPPORTED, "device index %d above 15", dev);
+  std::lock_guard<std::mutex> lk(g_mlp_mu);
+  SurrogateState& st = g_sur[dev];
+  hipStream_t s = (hipStream_t)stream;
+  if (!st.dev_ptr) MLP_HIP(hipMalloc((void**)&st.dev_ptr, sizeof(MlpDev)));
+  st.dev = dev;
+  st.band = (float)fallback_band;
+  st.k_lo = (float)k_lo;
+  st.k_hi = (float)k_hi;
+  const char* sp = getenv("PT_MLP_SPLIT");
+  st.split = (sp && sp[0] == '0') ? 0 : 1;
+  hipLaunchKernelGGL(k_mlp_pack, dim3(grid1(kH * kH)), dim3(256), 0, s, *w, st.dev_ptr);
+  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, s, st.dev_ptr, st.band, st.k_lo, st.k_hi, st.split);
+  uint8_t* cells = nullptr;
+  MLP_HIP(hipMallocAsync((void**)&cells, kTrustNC * kTrustNK, s));
+  const size_t lds = 4 * kMlpLdsPerWave;
+  const float tol = 8e-6f;
+  if (st.split) {
+    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_trust<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mlp_trust<1>, dim3(kTrustNC * kTrustNK / 4), dim3(256), lds, s, st.dev_ptr, tol, cells);
+  } else {
+    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_trust<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mlp_trust<0>, dim3(kTrustNC * kTrustNK / 4), dim3(256), lds, s, st.dev_ptr, tol, cells);
+  }
+  hipLaunchKernelGGL(k_pack_trust, dim3(grid1(kTrustNC * kTrustNK / 32)), dim3(256), 0, s, cells, st.dev_ptr);
+  std::vector<uint8_t> host(kTrustNC * kTrustNK);
+  MLP_HIP(hipMemcpyAsync(host.data(), cells, host.size(), hipMemcpyDeviceToHost, s));
+  MLP_HIP(hipStreamSynchronize(s));
+  hipFree(cells);
+  size_t ntr = 0;
+  for (uint8_t c : host) ntr += c;
+  st.trusted_fraction = (double)ntr / host.size();
+  st.ready = true;
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
+}
+
+pt_status pt_surrogate_eval(const double* zk, int64_t n, double* out, void* stream) {
+  if (n < 0) return set_error(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!zk || !out)) return set_error(PT_ERR_ARG, "zk or out is NULL");
+  int dev = 0;
+  MLP_HIP(hipGetDevice(&dev));
+  const MlpDev* m = surrogate_device_ptr(dev);
+  if (!m) return set_error(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
+  if (n == 0) return PT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t lds = 4 * kMlpLdsPerWave;
+  const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  if (surrogate_split(dev)) {
+    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_eval<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mlp_eval<1>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
+  } else {
+    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_eval<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mlp_eval<0>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
+  }
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
+}
+
+pt_status pt_mlp_infer(const float* zk, int64_t n, float* out, void* stream) {
+  if (n < 0) return set_error(PT_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!zk || !out)) return set_error(PT_ERR_ARG, "zk or out is NULL");
+  int dev = 0;
+  MLP_HIP(hipGetDevice(&dev));
+  const MlpDev* m = surrogate_device_ptr(dev);
+  if (!m) return set_error(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
+  if (n == 0) return PT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t lds = 4 * kMlpLdsPerWave;
+  const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  if (surrogate_split(dev)) {
+    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_infer<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mlp_infer<1>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
+  } else {
+    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_infer<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_mlp_infer<0>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
+  }
+  MLP_HIP(hipGetLastError());
+  return PT_OK;
+}
+
+double pt_surrogate_trusted_fraction(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1.0;
+  return surrogate_trusted_fraction(dev);
+}
+
+}  // extern "C"

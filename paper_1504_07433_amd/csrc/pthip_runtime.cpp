@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/pthip.h"
+#include "mlp_device.h"
 #include "pthip_internal.h"
 
 namespace pt {
@@ -46,6 +47,20 @@ static bool fault_injected() {
   const char* v = getenv("PT_FAULT_INJECT");
   return v && strcmp(v, "hip") == 0;
 }
+
+pt_status set_error(pt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+void surrogate_release();
+const MlpDev* surrogate_device_ptr(int dev);
+int surrogate_split(int dev);
 
 static pt_status ok() {
   g_err.clear();
@@ -127,6 +142,14 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
   return PT_OK;
 }
 
+// Interpolation table of PT_MODEL_MA_INTERP, one per device.
+struct MaTableState {
+  DevBuf buf;
+  MaTable t{};
+  bool ready = false;
+};
+static MaTableState g_matab[16];
+
 static int cu_count() {
   int dev = current_device();
   int cu = 0;
@@ -148,6 +171,7 @@ struct LaunchShape {
 struct TileSet {
   DevBuf tiles;
   int64_t n_tiles = 0;
+  DevBuf lc_tile_off, lc_tiles, partial;   // per light curve tile lists (likelihood)
 };
 
 struct Plan {
@@ -155,17 +179,18 @@ struct Plan {
   int32_t n_lc = 0, n_band = 0, nldc = 0, npol = 0, model = 0, prec = 0;
   std::vector<int64_t> t_count;
   std::vector<int32_t> nss, band_off;
-  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, oc, bc, gtab, queue;
+  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, bc, gtab, queue, khat;
   std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
   LaunchShape shape;
   bool tuned = false;
-  // captured graph for the last argument set
-  hipGraphExec_t exec = nullptr;
-  BatchArgs exec_args{};
-  int exec_workgroups = 0;
+  // captured graphs for the last argument set: [0] flux, [1] likelihood
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  BatchArgs exec_args[2]{};
+  int exec_workgroups[2] = {0, 0};
   hipStream_t capture_stream = nullptr;
   ~Plan() {
-    if (exec) hipGraphExecDestroy(exec);
+    for (auto& e : exec)
+      if (e) hipGraphExecDestroy(e);
     if (capture_stream) hipStreamDestroy(capture_stream);
   }
 };
@@ -202,10 +227,13 @@ static std::string plan_key(const pt_batch* b, int model, int npol, int prec) {
 
 static pt_status validate_batch(const pt_batch* b, pt_model model, int32_t npol, pt_prec prec) {
   if (!b) return fail(PT_ERR_ARG, "batch is NULL");
-  if (model != PT_MODEL_MA_QUAD && model != PT_MODEL_GIMENEZ) return fail(PT_ERR_ARG, "unknown model %d", (int)model);
+  if (model < PT_MODEL_MA_QUAD || model > PT_MODEL_MA_KHAT) return fail(PT_ERR_ARG, "unknown model %d", (int)model);
+  const bool ma_family = model != PT_MODEL_GIMENEZ;
+  if ((model == PT_MODEL_MA_INTERP || model == PT_MODEL_MA_KHAT) && prec != PT_PREC_FP32)
+    return fail(PT_ERR_UNSUPPORTED, "the interpolated and khat models run in PT_PREC_FP32 only");
   if (!valid_prec(prec)) return fail(PT_ERR_ARG, "unknown precision %d", (int)prec);
   if (b->n_lc < 0) return fail(PT_ERR_ARG, "n_lc = %d < 0", b->n_lc);
-  if (model == PT_MODEL_MA_QUAD && b->nldc != 2)
+  if (ma_family && b->nldc != 2)
     return fail(PT_ERR_ARG, "quadratic Mandel-Agol needs nldc = 2 (u1, u2), got %d", b->nldc);
   if (model == PT_MODEL_GIMENEZ && (b->nldc < 1 || b->nldc > 4))
     return fail(PT_ERR_ARG, "Gimenez needs 1 <= nldc <= 4, got %d", b->nldc);
@@ -277,6 +305,19 @@ static pt_status build_tiles(Plan* p, int tile_e, TileSet** out) {
   PT_HIP(ts->tiles.ensure(std::max<size_t>(1, tiles.size()) * sizeof(TileDesc)));
   if (!tiles.empty())
     PT_HIP(hipMemcpy(ts->tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
+  if (tiles.size() > 0x7fffffffu) return fail(PT_ERR_ARG, "more than 2^31 tiles; use larger tiles");
+  std::vector<int32_t> off(p->n_lc + 1, 0), lst(tiles.size());
+  for (const TileDesc& t : tiles) off[t.lc + 1]++;
+  for (int32_t i = 0; i < p->n_lc; ++i) off[i + 1] += off[i];
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (size_t j = 0; j < tiles.size(); ++j) lst[fill[tiles[j].lc]++] = (int32_t)j;
+  }
+  PT_HIP(ts->lc_tile_off.ensure(off.size() * 4));
+  PT_HIP(ts->lc_tiles.ensure(std::max<size_t>(1, lst.size()) * 4));
+  PT_HIP(ts->partial.ensure(std::max<size_t>(1, tiles.size()) * 8));
+  PT_HIP(hipMemcpy(ts->lc_tile_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+  if (!lst.empty()) PT_HIP(hipMemcpy(ts->lc_tiles.p, lst.data(), lst.size() * 4, hipMemcpyHostToDevice));
   *out = ts.get();
   p->tilesets[tile_e] = std::move(ts);
   return PT_OK;
@@ -321,17 +362,22 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   PT_HIP(p->d_nss.ensure(std::max<size_t>(1, n) * 4));
   PT_HIP(p->d_band_off.ensure((n + 1) * 4));
   PT_HIP(p->d_flux_off.ensure(std::max<size_t>(1, n) * 8));
+  PT_HIP(p->d_n_obs.ensure(std::max<size_t>(1, n) * 8));
   if (n) {
     PT_HIP(hipMemcpy(p->d_t_start.p, b->t_start, n * 8, hipMemcpyHostToDevice));
     PT_HIP(hipMemcpy(p->d_t_count.p, b->t_count, n * 8, hipMemcpyHostToDevice));
     PT_HIP(hipMemcpy(p->d_nss.p, b->nss, n * 4, hipMemcpyHostToDevice));
     PT_HIP(hipMemcpy(p->d_band_off.p, b->band_off, (n + 1) * 4, hipMemcpyHostToDevice));
     PT_HIP(hipMemcpy(p->d_flux_off.p, b->flux_off, n * 8, hipMemcpyHostToDevice));
+    std::vector<int64_t> nobs(n);
+    for (size_t i = 0; i < n; ++i) nobs[i] = (int64_t)(b->band_off[i + 1] - b->band_off[i]) * b->t_count[i];
+    PT_HIP(hipMemcpy(p->d_n_obs.p, nobs.data(), n * 8, hipMemcpyHostToDevice));
   }
   PT_HIP(p->oc.ensure(std::max<size_t>(1, n) * sizeof(OrbitConst)));
   PT_HIP(p->bc.ensure(std::max<size_t>(1, (size_t)p->n_band) * sizeof(BandConst)));
   PT_HIP(p->queue.ensure(64));
   PT_HIP(hipMemset(p->queue.p, 0, 64));
+  if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (model == PT_MODEL_GIMENEZ) {
     const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
     PT_HIP(p->gtab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * npol * es));
@@ -350,7 +396,8 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   return PT_OK;
 }
 
-static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, BatchArgs* a) {
+static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, BatchArgs* a,
+                           const void* obs = nullptr, const double* sigma = nullptr, double* loglike = nullptr) {
   TileSet* ts = nullptr;
   pt_status st = build_tiles(p, tile_e, &ts);
   if (st != PT_OK) return st;
@@ -368,11 +415,27 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
   a->bc = (BandConst*)p->bc.p;
   a->queue = (unsigned int*)p->queue.p;
   a->flux = flux;
+  if (obs) {
+    a->obs = obs;
+    a->sigma = sigma;
+    a->loglike = loglike;
+    a->partial = (double*)ts->partial.p;
+    a->lc_tile_off = (const int32_t*)ts->lc_tile_off.p;
+    a->lc_tiles = (const int32_t*)ts->lc_tiles.p;
+    a->n_obs = (const int64_t*)p->d_n_obs.p;
+  }
   a->n_lc = p->n_lc;
   a->n_band = p->n_band;
   a->nldc = p->nldc;
   a->npol = p->npol;
   a->model = p->model;
+  if (p->prec == PT_PREC_SURROGATE) a->mlp = surrogate_device_ptr(p->dev);
+  if (p->model == PT_MODEL_MA_KHAT) a->khat = (double*)p->khat.p;
+  if (p->model == PT_MODEL_MA_INTERP) {
+    if (p->dev < 0 || p->dev >= 16 || !g_matab[p->dev].ready)
+      return fail(PT_ERR_UNSUPPORTED, "no interpolation table on this device (pt_ma_table_set)");
+    a->matab = g_matab[p->dev].t;
+  }
   if (p->model == PT_MODEL_GIMENEZ) {
     GimTables* g = nullptr;
     st = gim_tables(p->nldc, p->npol, &g);
@@ -384,18 +447,30 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
   return PT_OK;
 }
 
+static int kernel_prec(const Plan* p) {
+  if (p->prec == PT_PREC_FP64) return kPrecFP64;
+  if (p->prec == PT_PREC_SURROGATE) return surrogate_split(p->dev) ? kPrecSurrogate : kPrecSurrogateBf16;
+  return kPrecFP32;
+}
+
 static bool use_graph() {
   const char* v = getenv("PT_NO_GRAPH");
   return !(v && v[0] == '1');
 }
 
 static pt_status run_plan(Plan* p, const BatchArgs& a, int workgroups, hipStream_t s) {
-  const int prec = p->prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
+  const int prec = kernel_prec(p);
+  static std::once_flag once;
+  static hipError_t prep_err = hipSuccess;
+  std::call_once(once, [] { prep_err = prepare_batch_kernels(); });
+  if (prep_err != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes: %s", hipGetErrorString(prep_err));
   if (!use_graph()) {
     PT_HIP(launch_batch(a, prec, p->model, workgroups, s));
     return PT_OK;
   }
-  if (!p->exec || memcmp(&p->exec_args, &a, sizeof a) != 0 || p->exec_workgroups != workgroups) {
+  const int gi = a.obs ? 1 : 0;
+  hipGraphExec_t& exec = p->exec[gi];
+  if (!exec || memcmp(&p->exec_args[gi], &a, sizeof a) != 0 || p->exec_workgroups[gi] != workgroups) {
     hipGraph_t g = nullptr;
     PT_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_batch(a, prec, p->model, workgroups, p->capture_stream);
@@ -405,20 +480,20 @@ static pt_status run_plan(Plan* p, const BatchArgs& a, int workgroups, hipStream
       return fail(PT_ERR_HIP, "launch during capture: %s", hipGetErrorString(le));
     }
     if (ce != hipSuccess) return fail(PT_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
-    if (p->exec) {
-      hipGraphExecDestroy(p->exec);
-      p->exec = nullptr;
+    if (exec) {
+      hipGraphExecDestroy(exec);
+      exec = nullptr;
     }
-    hipError_t ie = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (ie != hipSuccess) {
-      p->exec = nullptr;
+      exec = nullptr;
       return fail(PT_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
     }
-    p->exec_args = a;
-    p->exec_workgroups = workgroups;
+    p->exec_args[gi] = a;
+    p->exec_workgroups[gi] = workgroups;
   }
-  PT_HIP(hipGraphLaunch(p->exec, s));
+  PT_HIP(hipGraphLaunch(exec, s));
   return PT_OK;
 }
 
@@ -440,6 +515,8 @@ void pt_release(void) {
   g_plans.clear();
   g_gim.clear();
   g_tuned.clear();
+  for (auto& t : g_matab) { t.buf.release(); t.ready = false; }
+  surrogate_release();
 }
 
 int pt_device_cu_count(void) { return cu_count(); }
@@ -510,7 +587,9 @@ pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
                       void* stream) {
   pt_status st = validate_batch(batch, model, npol, prec);
   if (st != PT_OK) return st;
-  if (prec == PT_PREC_SURROGATE)
+  if (prec == PT_PREC_SURROGATE && model != PT_MODEL_MA_QUAD)
+    return fail(PT_ERR_UNSUPPORTED, "the surrogate covers the Mandel-Agol model only");
+  if (prec == PT_PREC_SURROGATE && !surrogate_device_ptr(current_device()))
     return fail(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
   if (batch->n_lc == 0 || batch->band_off[batch->n_lc] == batch->band_off[0]) return ok();
   if (batch->n_flux > 0 && !flux) return fail(PT_ERR_ARG, "flux is NULL");
@@ -521,6 +600,50 @@ pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   if (st != PT_OK) return st;
   BatchArgs a;
   st = fill_args(batch, p, p->shape.tile_e, flux, &a);
+  if (st != PT_OK) return st;
+  st = run_plan(p, a, p->shape.workgroups, (hipStream_t)stream);
+  if (st != PT_OK) return st;
+  return ok();
+}
+
+pt_status pt_ma_table_set(double k_lo, double k_hi, int32_t nk, int32_t nz, void* stream) {
+  if (!(k_lo > 0) || !(k_hi > k_lo) || !std::isfinite(k_hi)) return fail(PT_ERR_ARG, "need 0 < k_lo < k_hi");
+  if (nk < 2 || nz < 2 || (int64_t)nk * nz > (1 << 24)) return fail(PT_ERR_ARG, "need nk, nz >= 2 and nk*nz <= 2^24");
+  const int dev = current_device();
+  if (dev < 0 || dev >= 16) return fail(PT_ERR_UNSUPPORTED, "device index outside 0..15");
+  std::lock_guard<std::mutex> lk(g_mu);
+  MaTableState& st = g_matab[dev];
+  PT_HIP(st.buf.ensure((size_t)nk * nz * sizeof(float4)));
+  hipStream_t s = (hipStream_t)stream;
+  PT_HIP(launch_ma_table(k_lo, k_hi, nk, nz, (float4*)st.buf.p, s));
+  PT_HIP(hipStreamSynchronize(s));
+  st.t.tab = (const float4*)st.buf.p;
+  st.t.k_lo = (float)k_lo;
+  st.t.k_hi = (float)k_hi;
+  st.t.z_hi = (float)(1.0 + k_hi);
+  st.t.nk = nk;
+  st.t.nz = nz;
+  st.ready = true;
+  return ok();
+}
+
+pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec, const void* obs,
+                        const double* sigma, double* loglike, void* stream) {
+  pt_status st = validate_batch(batch, model, npol, prec);
+  if (st != PT_OK) return st;
+  if (prec == PT_PREC_SURROGATE && (model != PT_MODEL_MA_QUAD || !surrogate_device_ptr(current_device())))
+    return fail(PT_ERR_UNSUPPORTED, "surrogate not installed or not Mandel-Agol");
+  if (batch->n_lc == 0) return ok();
+  if (!sigma || !loglike) return fail(PT_ERR_ARG, "sigma or loglike is NULL");
+  if (batch->n_flux > 0 && !obs) return fail(PT_ERR_ARG, "obs is NULL");
+  if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Plan* p = nullptr;
+  st = get_plan(batch, model, npol, prec, &p, nullptr);
+  if (st != PT_OK) return st;
+  BatchArgs a;
+  // a non-null obs pointer selects the likelihood kernels, even for n_flux = 0
+  st = fill_args(batch, p, p->shape.tile_e, nullptr, &a, obs ? obs : (const void*)sigma, sigma, loglike);
   if (st != PT_OK) return st;
   st = run_plan(p, a, p->shape.workgroups, (hipStream_t)stream);
   if (st != PT_OK) return st;
@@ -543,8 +666,8 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
                       void* stream, char* report, size_t report_len) {
   pt_status st = validate_batch(batch, model, npol, prec);
   if (st != PT_OK) return st;
-  if (prec == PT_PREC_SURROGATE)
-    return fail(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
+  if (prec == PT_PREC_SURROGATE && (model != PT_MODEL_MA_QUAD || !surrogate_device_ptr(current_device())))
+    return fail(PT_ERR_UNSUPPORTED, "surrogate not installed or not Mandel-Agol");
   if (batch->n_lc == 0) return ok();
   if (batch->n_flux > 0 && !flux) return fail(PT_ERR_ARG, "flux is NULL");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -562,7 +685,11 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   std::string rep = "{\"candidates\": [";
   float best = 1e30f;
   LaunchShape best_shape = p->shape;
-  const int prec_k = prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
+  const int prec_k = kernel_prec(p);
+  {
+    hipError_t pe = prepare_batch_kernels();
+    if (pe != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes: %s", hipGetErrorString(pe));
+  }
   bool first = true;
   for (int te : tiles) {
     BatchArgs a;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpthip.so")
 
 PT_OK, PT_ERR_ARG, PT_ERR_HIP, PT_ERR_NOMEM, PT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 PREC = {"fp64": 0, "fp32": 1, "surrogate": 2}
-MODEL = {"ma": 0, "gimenez": 1}
+MODEL = {"ma": 0, "gimenez": 1, "ma_interp": 2, "ma_khat": 3}
 
 
 class PthipError(RuntimeError):
@@ -58,6 +58,8 @@ def _load():
         "pt_ma_quad": (st, [vp, i64, d, vp, i32, C.c_int, vp, vp]),
         "pt_gimenez": (st, [vp, i64, d, vp, i32, i32, i32, C.c_int, vp, vp]),
         "pt_lc_batch": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp]),
+        "pt_ma_table_set": (st, [d, d, i32, i32, vp]),
+        "pt_lc_loglike": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp, vp, vp]),
         "pt_autotune": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp, C.c_char_p, C.c_size_t]),
         "pt_batch_launch_shape": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int,
                                        C.POINTER(i32), C.POINTER(i32)]),
@@ -66,8 +68,11 @@ def _load():
         "pt_mlp_backward": (st, [C.POINTER(PtMlp), vp, vp, vp, i64, C.POINTER(PtMlp), vp]),
         "pt_mlp_adam_step": (st, [C.POINTER(PtMlp), C.POINTER(PtMlp), C.POINTER(PtMlp),
                                   C.POINTER(PtMlp), i64, f, f, f, f, vp]),
+        "pt_mlp_loss_grad": (st, [vp, vp, vp, i64, vp, vp, vp]),
         "pt_surrogate_set": (st, [C.POINTER(PtMlp), d, d, d, vp]),
+        "pt_surrogate_trusted_fraction": (d, []),
         "pt_surrogate_eval": (st, [vp, i64, vp, vp]),
+        "pt_mlp_infer": (st, [vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -79,8 +84,9 @@ def _load():
 lib = _load()
 SYMBOLS = [
     "pt_version", "pt_last_error", "pt_release", "pt_device_cu_count", "pt_orbit_z", "pt_ma_quad",
-    "pt_gimenez", "pt_lc_batch", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
-    "pt_mlp_forward", "pt_mlp_backward", "pt_mlp_adam_step", "pt_surrogate_set", "pt_surrogate_eval",
+    "pt_gimenez", "pt_ma_table_set", "pt_lc_batch", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
+    "pt_mlp_forward", "pt_mlp_backward", "pt_mlp_loss_grad", "pt_mlp_adam_step", "pt_surrogate_set",
+    "pt_surrogate_trusted_fraction", "pt_surrogate_eval", "pt_mlp_infer",
 ]
 
 
@@ -193,6 +199,23 @@ def lc_batch(batch: DeviceBatch, model="ma", npol=50, prec="fp32", out=None):
     return out
 
 
+def ma_table_set(k_lo, k_hi, nk=128, nz=256):
+    _check(lib.pt_ma_table_set(k_lo, k_hi, nk, nz, _stream()))
+
+
+def lc_loglike(batch: DeviceBatch, obs, sigma, model="ma", npol=50, prec="fp32", out=None):
+    """Per-light-curve Gaussian log-likelihood of obs (pt_lc_batch layout)."""
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    assert obs.dtype == dtype and obs.is_cuda
+    sigma = _dev64(sigma)
+    if out is None:
+        out = torch.empty(batch.n_lc, dtype=torch.float64, device=obs.device)
+    s = batch.struct()
+    _check(lib.pt_lc_loglike(C.byref(s), MODEL[model], npol, PREC[prec], _ptr(obs), _ptr(sigma), _ptr(out),
+                             _stream()))
+    return out
+
+
 def autotune(batch: DeviceBatch, model="ma", npol=50, prec="fp32", out=None):
     dtype = torch.float64 if prec == "fp64" else torch.float32
     if out is None:
@@ -209,3 +232,71 @@ def launch_shape(batch: DeviceBatch, model="ma", npol=50, prec="fp32"):
     te, wg = C.c_int32(), C.c_int32()
     _check(lib.pt_batch_launch_shape(C.byref(s), MODEL[model], npol, PREC[prec], C.byref(te), C.byref(wg)))
     return te.value, wg.value
+
+
+# -- surrogate -------------------------------------------------------------------------
+
+MLP_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+MLP_SHAPES = {"W1": (128, 2), "b1": (128,), "W2": (128, 128), "b2": (128,), "W3": (128, 128),
+              "b3": (128,), "W4": (3, 128), "b4": (3,)}
+
+
+def mlp_struct(params) -> PtMlp:
+    """params: dict name -> contiguous float32 cuda tensor."""
+    s = PtMlp()
+    for n in MLP_NAMES:
+        t = params[n]
+        assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous() and tuple(t.shape) == MLP_SHAPES[n]
+        setattr(s, n, _ptr(t))
+    return s
+
+
+def mlp_datagen(zk):
+    zk = _dev64(zk).reshape(-1, 2)
+    out = torch.empty((zk.shape[0], 3), dtype=torch.float64, device=zk.device)
+    _check(lib.pt_mlp_datagen(_ptr(zk), zk.shape[0], _ptr(out), _stream()))
+    return out
+
+
+def mlp_forward(params, zk32, act=None):
+    n = zk32.shape[0]
+    out = torch.empty((n, 3), dtype=torch.float32, device=zk32.device)
+    s = mlp_struct(params)
+    _check(lib.pt_mlp_forward(C.byref(s), _ptr(zk32), n, _ptr(out), _ptr(act), _stream()))
+    return out
+
+
+def mlp_backward(params, zk32, act, dout, grads):
+    s, g = mlp_struct(params), mlp_struct(grads)
+    _check(lib.pt_mlp_backward(C.byref(s), _ptr(zk32), _ptr(act), _ptr(dout), zk32.shape[0], C.byref(g),
+                               _stream()))
+
+
+def mlp_loss_grad(out, zk32, alpha, dout, loss):
+    _check(lib.pt_mlp_loss_grad(_ptr(out), _ptr(zk32), _ptr(alpha), out.shape[0], _ptr(dout), _ptr(loss),
+                                _stream()))
+
+
+def mlp_adam_step(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    sp, sg, sm, sv = (mlp_struct(x) for x in (params, grads, m, v))
+    _check(lib.pt_mlp_adam_step(C.byref(sp), C.byref(sg), C.byref(sm), C.byref(sv), int(step), lr, beta1,
+                                beta2, eps, _stream()))
+
+
+def surrogate_set(params, fallback_band=1e-3, k_lo=0.01, k_hi=0.3):
+    s = mlp_struct(params)
+    _check(lib.pt_surrogate_set(C.byref(s), fallback_band, k_lo, k_hi, _stream()))
+    return lib.pt_surrogate_trusted_fraction()
+
+
+def surrogate_eval(zk):
+    zk = _dev64(zk).reshape(-1, 2)
+    out = torch.empty((zk.shape[0], 3), dtype=torch.float64, device=zk.device)
+    _check(lib.pt_surrogate_eval(_ptr(zk), zk.shape[0], _ptr(out), _stream()))
+    return out
+
+
+def mlp_infer(zk32):
+    out = torch.empty((zk32.shape[0], 3), dtype=torch.float32, device=zk32.device)
+    _check(lib.pt_mlp_infer(_ptr(zk32), zk32.shape[0], _ptr(out), _stream()))
+    return out

@@ -1,0 +1,135 @@
+"""Surrogate network on the GPU: exact targets, float forward/backward against
+the FP64 numpy reference, the bf16-MFMA inference against the float forward
+(which checks the MFMA operand layout), training, and the trust map's
+guarantee that surrogate results stay within tolerance."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1504_07433_amd import pthip
+    return pthip
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _params(pt, seed=0):
+    import torch
+    from oracle import mlp_ref as R
+    w = R.init_weights(seed)
+    return w, {n: torch.as_tensor(w[n], dtype=torch.float32, device="cuda").contiguous() for n in R.NAMES}
+
+
+def _zk(n, seed=1):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(0, 1.35, n), rng.uniform(0.01, 0.3, n)], 1)
+
+
+def test_datagen_matches_oracle(pt):
+    from oracle import oracle as O
+    zk = _zk(3000)
+    zk[:10, 0] = zk[:10, 1]                  # z = k exactly
+    zk[10:20, 0] = 1 - zk[10:20, 1]          # z = 1 - k
+    got = pt.mlp_datagen(zk).cpu().numpy()
+    ref = O.surrogate_targets(zk)
+    assert np.abs(got - ref).max() <= 1e-10
+
+
+def test_forward_and_backward_match_reference(pt):
+    import torch
+    from oracle import mlp_ref as R
+    w, P = _params(pt, 3)
+    zk = _zk(5000, 2)
+    alpha = np.abs(np.random.default_rng(0).normal(0, 0.02, (5000, 3)))
+    zk32 = torch.as_tensor(zk, dtype=torch.float32, device="cuda").contiguous()
+    act = torch.empty((5000, 3, 128), dtype=torch.float32, device="cuda")
+    y = pt.mlp_forward(P, zk32, act).cpu().numpy()
+    zk_f = zk.astype(np.float32).astype(np.float64)
+    yref, _ = R.forward(w, zk_f)
+    assert np.abs(y - yref).max() <= 2e-5 * max(1.0, np.abs(yref).max())
+    dout = torch.empty((5000, 3), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    a_dev = torch.as_tensor(alpha, device="cuda")
+    pt.mlp_loss_grad(pt.mlp_forward(P, zk32, act), zk32, a_dev, dout, loss)
+    assert loss.item() == pytest.approx(R.loss(w, zk_f, alpha), rel=1e-4)
+    grads = {n: torch.zeros_like(t) for n, t in P.items()}
+    pt.mlp_backward(P, zk32, act, dout, grads)
+    gref = R.grad(w, zk_f, alpha)
+    for n in R.NAMES:
+        g = grads[n].cpu().numpy()
+        scale = np.abs(gref[n]).max()
+        assert np.abs(g - gref[n]).max() <= 1e-3 * scale + 1e-9, n
+
+
+def test_adam_step_matches_definition(pt):
+    import torch
+    w, P = _params(pt, 4)
+    grads = {n: torch.full_like(t, 0.5) for n, t in P.items()}
+    m = {n: torch.zeros_like(t) for n, t in P.items()}
+    v = {n: torch.zeros_like(t) for n, t in P.items()}
+    before = {n: t.clone() for n, t in P.items()}
+    pt.mlp_adam_step(P, grads, m, v, 1, 1e-2)
+    for n in P:   # first step: w -= lr * g/|g| (bias-corrected moments)
+        d = (before[n] - P[n]).cpu().numpy()
+        assert np.allclose(d, 1e-2, rtol=1e-4)
+
+
+def test_mfma_inference_matches_float_forward(pt):
+    import torch
+    w, P = _params(pt, 5)
+    pt.surrogate_set(P)
+    zk32 = torch.as_tensor(_zk(4096, 6), dtype=torch.float32, device="cuda").contiguous()
+    y_inf = pt.mlp_infer(zk32).cpu().numpy()
+    y_fwd = pt.mlp_forward(P, zk32).cpu().numpy()
+    err = np.abs(y_inf - y_fwd).max() / np.abs(y_fwd).max()
+    say("mfma vs float forward, relative", err)
+    assert err <= 2e-4
+
+
+def test_training_reduces_loss_and_trust_map_holds(pt):
+    import torch
+    from oracle import oracle as O
+    from paper_1504_07433_amd.surrogate import Surrogate
+    s = Surrogate(seed=5)
+    zk32, alpha = s.make_data(400_000, seed=5)
+    hist = s.train(zk32, alpha, steps=600, batch=16384, log_every=100)
+    say("loss history", hist)
+    assert hist[-1][1] < 0.05 * hist[0][1]
+    frac = s.install()
+    say("trusted fraction", frac)
+    assert 0.0 <= frac <= 1.0
+    # surrogate values (network where trusted, exact elsewhere) are within the
+    # flux tolerance for every quadratic law with uniform-(q1,q2) coefficients
+    zk = _zk(20000, 9)
+    got = pt.surrogate_eval(zk).cpu().numpy()
+    ref = O.surrogate_targets(zk.astype(np.float32).astype(np.float64))
+    bound = 2 * np.abs(got[:, 0] - ref[:, 0]) + 4 * np.abs(got[:, 1] - ref[:, 1]) + 2 * np.abs(got[:, 2] - ref[:, 2])
+    say("surrogate bound max", bound.max())
+    assert bound.max() <= 1e-5
+
+
+def test_batch_surrogate_parity(pt):
+    from oracle import oracle as O
+    from paper_1504_07433_amd import workloads as W
+    from paper_1504_07433_amd.surrogate import Surrogate
+    s = Surrogate(seed=6)
+    zk32, alpha = s.make_data(200_000, seed=6)
+    s.train(zk32, alpha, steps=300, batch=16384, log_every=0)
+    s.install()
+    b = W.config3(n_vec=4, n_band=64, n_exp=1500)
+    ref = O.lc_batch(b, model=0)
+    db = pt.DeviceBatch(b)
+    got = pt.lc_batch(db, "ma", prec="surrogate").cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max()
+    say("batch surrogate max|dF|", err)
+    assert err <= 1e-5
+    b2 = W.config2(n_vec=4, n_windows=2)
+    got2 = pt.lc_batch(pt.DeviceBatch(b2), "ma", prec="surrogate").cpu().numpy().astype(np.float64)
+    assert np.abs(got2 - O.lc_batch(b2, model=0)).max() <= 1e-5

@@ -282,3 +282,38 @@ def test_golden_fixture_is_well_formed():
         g = json.load(fh)
     for item in g["items"]:
         assert item["citation"] and "value" in item
+
+
+# --- paper-printed error levels of the interpolated model (Sect. 2.2.3) ------------------
+
+def _golden(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")
+    with open(path) as fh:
+        return {i["name"]: i for i in json.load(fh)["items"]}[name]
+
+
+def test_interpolated_ma_error_matches_paper_order(oracle):
+    """Bilinear tables of the three functions over a k range of 0.02
+    (n_k = 128, n_z = 256) deviate from the direct model by a few ppm at most
+    and by a small fraction of a ppm on average; n_k = 8 changes little."""
+    g_max, g_mean = _golden("ma_interp_max_abs_error"), _golden("ma_interp_mean_abs_error")
+    g_nk8 = _golden("ma_interp_max_abs_error_nk8")
+    k_lo, k_hi = 0.10, 0.12
+    u1, u2 = 0.4, 0.2
+    c = u1 + 2 * u2
+    w = np.array([1 - c, c, u2]) / (1 - u1 / 3 - u2 / 6)
+    rng = np.random.default_rng(0)
+    res = {}
+    for nk in (128, 8):
+        tab = oracle.ma_table(k_lo, k_hi, nk, 256)
+        errs = []
+        for k in rng.uniform(k_lo, k_hi, 3):
+            z = np.linspace(0, 1 + k, 3000)[:-1]
+            ex = oracle.ma_alpha_many(z, np.full(len(z), k)) @ w
+            ip = np.array([oracle.ma_interp_alpha(zz, k, tab, k_lo, k_hi) for zz in z]) @ w
+            errs.append(np.abs(ex - ip))
+        e = np.concatenate(errs)
+        res[nk] = (e.max(), e.mean())
+    assert g_max["value"] / 4 <= res[128][0] <= 4 * g_max["value"]
+    assert g_mean["value"] / 10 <= res[128][1] <= 10 * g_mean["value"]
+    assert g_nk8["value"] / 4 <= res[8][0] <= 4 * g_nk8["value"]

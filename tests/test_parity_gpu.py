@@ -277,3 +277,57 @@ def test_full_uneven_sampled(pt, O):
     from paper_1504_07433_amd import workloads as W
     b = W.config4()
     _sampled_check(pt, O, b, "ma", "fp32", TOL32, 1500)
+
+
+# --- fused likelihood -------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,ftol", [("fp32", TOL32), ("fp64", TOL64)])
+def test_loglike_matches_oracle(pt, O, prec, ftol):
+    import torch
+    from paper_1504_07433_amd import workloads as W
+    b = W.config4(n_lc=24, n_min=100, n_max=2000)
+    b["nss"][3] = 19                            # the per-band orbit branch too
+    F = O.lc_batch(b, model=0)
+    rng = np.random.default_rng(0)
+    sigma = rng.uniform(5e-4, 2e-3, len(b["t_start"]))
+    nb = np.diff(b["band_off"]).astype(np.int64)
+    sig_pt = np.repeat(sigma, nb * b["t_count"])
+    obs = F + rng.normal(0, 1, len(F)) * sig_pt
+    dtype = np.float32 if prec == "fp32" else np.float64
+    obs = obs.astype(dtype)
+    ref = O.loglike(b, obs.astype(np.float64), sigma, flux=F)
+    db = pt.DeviceBatch(b)
+    got = pt.lc_loglike(db, torch.as_tensor(obs, device="cuda"), sigma, prec=prec).cpu().numpy()
+    # each model value may differ by ftol: |d log L| <= sum |r| ftol/sigma + N (ftol/sigma)^2
+    for i in range(len(ref)):
+        sl = slice(b["flux_off"][i], b["flux_off"][i] + nb[i] * b["t_count"][i])
+        r = (obs[sl].astype(np.float64) - F[sl]) / sigma[i]
+        bound = np.abs(r).sum() * ftol / sigma[i] + len(r) * (ftol / sigma[i]) ** 2 + 1e-9 * abs(ref[i])
+        assert abs(got[i] - ref[i]) <= bound, (i, got[i], ref[i], bound)
+    # deterministic
+    again = pt.lc_loglike(db, torch.as_tensor(obs, device="cuda"), sigma, prec=prec).cpu().numpy()
+    assert np.array_equal(got, again)
+
+
+# --- paper variants: interpolated Mandel-Agol and the khat approximation -----------------
+
+def test_interpolated_model_matches_oracle(pt, O):
+    from paper_1504_07433_amd import workloads as W
+    k_lo, k_hi, nk, nz = 0.09, 0.11, 16, 64
+    pt.ma_table_set(k_lo, k_hi, nk, nz)
+    tab = O.ma_table(k_lo, k_hi, nk, nz)
+    b = W.config3(n_vec=3, n_band=8, n_exp=300)
+    b["k"][0] = 0.2                            # outside the table: exact path
+    ref = O.lc_batch_ma_variant(b, "interp", tab, k_lo, k_hi)
+    got = _run(pt, b, "ma_interp", "fp32")
+    assert np.abs(got - ref).max() <= TOL32
+
+
+def test_khat_model_matches_oracle(pt, O):
+    from paper_1504_07433_amd import workloads as W
+    b = W.config3(n_vec=3, n_band=8, n_exp=300)
+    ref = O.lc_batch_ma_variant(b, "khat")
+    got = _run(pt, b, "ma_khat", "fp32")
+    assert np.abs(got - ref).max() <= TOL32
+    exact = O.lc_batch(b, model=0)
+    say("khat approximation vs per-band k: max|dF|", np.abs(ref - exact).max())
