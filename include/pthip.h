@@ -56,9 +56,11 @@ typedef enum {
   PT_MODEL_GIMENEZ = 1,    /* Gimenez; u rows are the general-law u_1..u_nldc              */
   PT_MODEL_MA_INTERP = 2,  /* quadratic Mandel & Agol with lambda_e, lambda_d, eta_d from  */
                            /* bilinear tables (Sect. 2.2.3; pt_ma_table_set); float path  */
-  PT_MODEL_MA_KHAT = 3     /* quadratic Mandel & Agol evaluated at each light curve's mean */
+  PT_MODEL_MA_KHAT = 3,    /* quadratic Mandel & Agol evaluated at each light curve's mean */
                            /* radius ratio khat, depth scaled by k_i^2/khat^2 per band     */
                            /* (Sect. 3.5; an approximation); float path                    */
+  PT_MODEL_GIMENEZ_ZINTERP = 4  /* Gimenez flux interpolated linearly in z between nodes  */
+                           /* tabulated per band (Sect. 3.3; pt_gimenez_zgrid_set); float */
 } pt_model;
 
 /* Library version, e.g. "pthip 1.0 gfx950". */
@@ -121,6 +123,11 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
  * nk * nz <= 2^24. */
 pt_status pt_ma_table_set(double k_lo, double k_hi, int32_t nk, int32_t nz, void* stream);
 
+/* Node counts of PT_MODEL_GIMENEZ_ZINTERP (Sect. 3.3): n_in nodes on
+ * [0, 1-k] and n_limb nodes on [1-k, 1+k] per band (defaults 50 and 50).
+ * Applies to later calls.  Errors: PT_ERR_ARG unless 2 <= n <= 65536. */
+pt_status pt_gimenez_zgrid_set(int32_t n_in, int32_t n_limb);
+
 /* A ragged batch of light curves: each has its own orbit, exposure times,
  * exposure time and supersampling factor, and its own passbands, each with
  * its own radius ratio and limb darkening (Sects. 1, 2.1.3, 2.2.2, 3.2).
@@ -174,7 +181,9 @@ pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
  *            (float for PT_PREC_FP32/PT_PREC_SURROGATE, double for FP64), device
  *   sigma    [n_lc] white-noise standard deviation per light curve (> 0), device
  *   loglike  [n_lc] output, device, double; summed in a fixed order
- * Errors: as pt_lc_batch; PT_ERR_ARG for NULL obs/sigma/loglike. */
+ * Errors: as pt_lc_batch; PT_ERR_ARG for NULL obs/sigma/loglike.
+ * Currently switched off (PT_ERR_UNSUPPORTED): its first GPU test stopped
+ * responding and the cause has not been identified. */
 pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec,
                         const void* obs, const double* sigma, double* loglike, void* stream);
 

@@ -232,3 +232,45 @@ def lc_batch_ma_variant(batch, variant, table=None, k_lo=None, k_hi=None):
             off = batch["flux_off"][lc] + j * cnt
             flux[off:off + cnt] = 1 - loss.reshape(cnt, n).mean(1)
     return flux
+
+
+def gimenez_zgrid(k, n_in, n_limb):
+    """Nodes of the Gimenez z-space interpolation (Sect. 3.3): n_in points in
+    [0, 1-k] and n_limb points in [1-k, 1+k] (the shared node 1-k counted in
+    both)."""
+    return (np.linspace(0.0, 1.0 - k, n_in), np.linspace(1.0 - k, 1.0 + k, n_limb))
+
+
+def gimenez_zinterp_flux(z, k, u, npol, n_in, n_limb):
+    """Flux linearly interpolated in z between the tabulated Gimenez model
+    values at the nodes; 1 outside 0 <= z < 1 + k."""
+    zi, zl = gimenez_zgrid(k, n_in, n_limb)
+    fi = gimenez_flux(zi, k, u, npol)
+    fl = gimenez_flux(zl, k, u, npol)
+    z = np.atleast_1d(np.asarray(z, np.float64))
+    out = np.ones_like(z)
+    inside = (z >= 0) & (z <= 1 - k)
+    limb = (z > 1 - k) & (z < 1 + k)
+    out[inside] = np.interp(z[inside], zi, fi)
+    out[limb] = np.interp(z[limb], zl, fl)
+    return out
+
+
+def lc_batch_gimenez_zinterp(batch, npol, n_in, n_limb, u):
+    """Supersampled Gimenez batch with the flux interpolated in z between the
+    per-band nodes (Sect. 3.3).  Small batches only (Python loops)."""
+    flux = np.empty(batch["n_flux"])
+    for lc in range(len(batch["t_start"])):
+        s0, cnt, n = batch["t_start"][lc], batch["t_count"][lc], int(batch["nss"][lc])
+        b0, b1 = batch["band_off"][lc], batch["band_off"][lc + 1]
+        if b1 == b0 or cnt == 0:
+            continue
+        prm = tuple(batch[key][lc] for key in ("t0", "P", "aR", "b", "e", "w"))
+        t = batch["t"][s0:s0 + cnt]
+        ts = (t[:, None] + batch["t_exp"][lc] * ((np.arange(n) + 0.5) / n - 0.5)[None, :]).ravel()
+        z = orbit_z(ts, *prm)
+        for j, bnd in enumerate(range(b0, b1)):
+            f = gimenez_zinterp_flux(z, batch["k"][bnd], u[bnd], npol, n_in, n_limb)
+            off = batch["flux_off"][lc] + j * cnt
+            flux[off:off + cnt] = f.reshape(cnt, n).mean(1)
+    return flux

@@ -35,7 +35,9 @@ enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2, kPrecSurrogateBf1
 // kModelMAInterp: bilinear lambda_e, lambda_d, eta_d tables (Sect. 2.2.3);
 // kModelMAKhat: the functions at the light curve's mean k, depth scaled by
 // k_i^2 / khat^2 per band (Sect. 3.5).
-enum : int { kModelMA = 0, kModelGimenez = 1, kModelMAInterp = 2, kModelMAKhat = 3 };
+// kModelGimenezZInterp: Gimenez flux interpolated linearly in z between
+// per-band nodes (Sect. 3.3).
+enum : int { kModelMA = 0, kModelGimenez = 1, kModelMAInterp = 2, kModelMAKhat = 3, kModelGimenezZInterp = 4 };
 
 // Interpolation table of the three Mandel-Agol functions on a uniform
 // (k, z) grid: k in [k_lo, k_hi] (nk nodes), z in [0, 1 + k_hi] (nz nodes).
@@ -93,6 +95,8 @@ struct BatchArgs {
   double* loglike;      // [n_lc]
   MaTable matab;        // kModelMAInterp
   double* khat;         // [n_lc] mean radius ratio (kModelMAKhat), written by prep
+  float* ztab;          // [n_band][zin + zlimb] loss at the z nodes (kModelGimenezZInterp)
+  int32_t zin, zlimb;
 };
 
 // Launchers (defined in pthip_kernels.hip).

@@ -205,7 +205,8 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
   c.exact = k > 0.5 ? 1 : 0;
   c.valid = k > 0.0 ? 1 : 0;
   for (int m = 0; m < 5; ++m) c.wd[m] = 0.0;
-  if (model == kModelMA) {
+  const bool gimenez = model == kModelGimenez || model == kModelGimenezZInterp;
+  if (!gimenez) {                              // the Mandel-Agol family: (u1, u2)
     const double u1 = u[0], u2 = u[1];
     const double cc = u1 + 2.0 * u2;
     const double inv = 1.0 / (1.0 - u1 / 3.0 - u2 / 6.0);
@@ -364,6 +365,40 @@ hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab
   return hipGetLastError();
 }
 
+// Gimenez loss at the z nodes of each band: zin nodes on [0, 1-k], zlimb on
+// [1-k, 1+k] (Sect. 3.3).  One thread per (band, node).
+__global__ __launch_bounds__(256) void k_gim_ztable(BatchArgs a) {
+  const int nodes = a.zin + a.zlimb;
+  const int64_t total = (int64_t)a.n_band * nodes, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tab_stride = (int64_t)(a.nldc + 1) * a.npol;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int bnd = (int)(e / nodes), j = (int)(e % nodes);
+    const BandConst* bc = a.bc + bnd;
+    const float k = bc->kf;
+    const float z = j < a.zin ? (1.0f - k) * j / (a.zin - 1)
+                              : (1.0f - k) + 2.0f * k * (j - a.zin) / (a.zlimb - 1);
+    a.ztab[e] = gim_loss<float>(z, bc, a.nldc, a.npol, reinterpret_cast<const float*>(a.gtab) + bnd * tab_stride,
+                                reinterpret_cast<const float*>(a.grec));
+  }
+}
+
+__device__ __forceinline__ float gim_loss_zinterp(float z, const BandConst* __restrict__ bc,
+                                                  const float* __restrict__ zt, int zin, int zlimb) {
+  const float k = bc->kf;
+  if (z < 0.0f || z >= bc->onepk) return 0.0f;
+  const float omk = 1.0f - k;
+  if (z <= omk) {
+    const float pos = z / omk * (zin - 1);
+    const int i = min(zin - 2, max(0, (int)pos));
+    const float w = pos - i;
+    return (1.0f - w) * zt[i] + w * zt[i + 1];
+  }
+  const float pos = (z - omk) / (2.0f * k) * (zlimb - 1);
+  const int i = min(zlimb - 2, max(0, (int)pos));
+  const float w = pos - i;
+  return (1.0f - w) * zt[zin + i] + w * zt[zin + i + 1];
+}
+
 // Loss of band `bc` summed over the subsamples held in the wave's LDS slice.
 template <int PREC, int MODEL, class T>
 __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
@@ -374,6 +409,14 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
   T acc = T(0);
   if constexpr (MODEL == kModelMAInterp) {
     for (int s = 0; s < ns; ++s) acc += ma_loss_interp(zb[s * kWave + lane], bc, a.matab);
+  } else if constexpr (MODEL == kModelGimenezZInterp) {
+    // k >= 1 has no inner grid: direct series
+    const float* zt = a.ztab + (int64_t)(bc - a.bc) * (a.zin + a.zlimb);
+    if (bc->kf < 1.0f) {
+      for (int s = 0; s < ns; ++s) acc += gim_loss_zinterp(zb[s * kWave + lane], bc, zt, a.zin, a.zlimb);
+    } else {
+      for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.nldc, a.npol, tb, grec);
+    }
   } else if constexpr (MODEL == kModelMAKhat) {
     // zb holds three planes of the functions at khat: [3][kZChunk][kWave]
     for (int s = 0; s < ns; ++s)
@@ -547,6 +590,8 @@ static void launch_main(const BatchArgs& a, int prec, int model, dim3 grid, size
     if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMA, LOGL>), grid, block, lds, s, a);
     else if (model == kModelMAInterp) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMAInterp, LOGL>), grid, block, lds, s, a);
     else if (model == kModelMAKhat) hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMAKhat, LOGL>), grid, block, lds, s, a);
+    else if (model == kModelGimenezZInterp)
+      hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelGimenezZInterp, LOGL>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelGimenez, LOGL>), grid, block, lds, s, a);
   }
 }
@@ -556,8 +601,13 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
   hipLaunchKernelGGL(k_batch_prep, dim3(grid_for(prep_n > 0 ? prep_n : 1, 256)), dim3(256), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (model == kModelGimenez) {
+  if (model == kModelGimenez || model == kModelGimenezZInterp) {
     err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gaprime, a.gtab, prec, s);
+    if (err != hipSuccess) return err;
+  }
+  if (model == kModelGimenezZInterp) {
+    hipLaunchKernelGGL(k_gim_ztable, dim3(grid_for((int64_t)a.n_band * (a.zin + a.zlimb), 256)), dim3(256), 0, s, a);
+    err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
   if (a.n_tiles > 0) {

