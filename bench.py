@@ -45,7 +45,58 @@ def parse():
     ap.add_argument("--no-side", action="store_true", help="skip the side paths")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
+    ap.add_argument("--mode", choices=("full", "kernel", "units"), default="full",
+                    help="kernel: only the timed batch launches (for profilers); units: divergence-free "
+                         "launches of each unit of work, for counting operations per unit")
     return ap.parse_args()
+
+
+def unit_probes():
+    """Launches in which every lane takes the same path, so that hardware
+    operation counters divided by the number of units give operations per unit:
+    U1 circular orbit, all points inside the disc; U2 the same orbit with the
+    planet never on the disc; U3/U4 the same with e = 0.2; U5 limb crossings;
+    U6 Gimenez (npol = 50) inside the disc.  One band, one subsample, 2^21
+    exposures each, two launches each."""
+    import torch
+    from paper_1504_07433_amd import pthip, workloads as W
+
+    def one_lc(b_imp, e, k, n=1 << 21, span=0.01, aR=10.0):
+        b = W.config1()
+        b["t"] = np.linspace(-span, span, n)
+        b["t_count"] = np.array([n], np.int64)
+        b["nss"] = np.array([1], np.int32)
+        b["t_exp"] = np.array([0.0])
+        b["b"] = np.array([b_imp]); b["e"] = np.array([e]); b["w"] = np.array([1.0])
+        b["aR"] = np.array([aR]); b["P"] = np.array([3.0]); b["t0"] = np.array([0.0])
+        b["k"] = np.array([k]); b["u"] = np.array([[0.4, 0.2]]); b["n_flux"] = n
+        return b
+    cases = [("U1 circular inside", one_lc(0.3, 0.0, 0.1), "ma"),
+             ("U2 circular out", one_lc(1.5, 0.0, 0.1), "ma"),
+             ("U3 eccentric inside", one_lc(0.3, 0.2, 0.1), "ma"),
+             ("U4 eccentric out", one_lc(1.5, 0.2, 0.1), "ma"),
+             ("U5 circular limb", one_lc(0.99, 0.0, 0.1, span=0.002), "ma"),
+             ("U6 gimenez inside", one_lc(0.3, 0.0, 0.1), "gimenez")]
+    out = {}
+    for name, b, model in cases:
+        u = None
+        if model == "gimenez":
+            u = np.stack([b["u"][:, 0] + 2 * b["u"][:, 1], -b["u"][:, 1]], 1)
+        db = pthip.DeviceBatch(b, u=u)
+        for _ in range(2):
+            f = pthip.lc_batch(db, model, npol=50, prec="fp32")
+        torch.cuda.synchronize()
+        fh = f.cpu().numpy()
+        out[name] = {"units": int(b["n_flux"]), "in_transit_fraction": float((fh < 1).mean())}
+        print(json.dumps({"probe": name, **out[name]}), flush=True)
+    # a plain copy of 1 GiB: the reference for the HBM byte counters
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy 1 GiB"}), flush=True)
+    return out
 
 
 def timed(fn, steps, warmup):
@@ -124,6 +175,9 @@ def main():
     import torch
     from paper_1504_07433_amd import pthip, workloads as W
     torch.cuda.set_device(0)
+    if args.mode == "units":
+        unit_probes()
+        return
 
     batch = W.config2()
     db = pthip.DeviceBatch(batch)
@@ -137,6 +191,9 @@ def main():
     value = points * args.steps / wall
     kernel_s = gpu_s / args.steps
     tile_e, wg = pthip.launch_shape(db, "ma", prec="fp32")
+    if args.mode == "kernel":
+        print(json.dumps({"mode": "kernel", "ms_per_step": ms, "points_per_s": value}), flush=True)
+        return
 
     n_orbit, n_in = count_units(pthip, batch)
     n_out = points - n_in
@@ -183,6 +240,20 @@ def main():
         paths["gimenez50_fp32_spectrophotometric"] = {
             "workload": b3["name"], "points_per_s": p3 * 5 / w3g, "ms_per_step": w3g / 5 * 1e3,
             "max_abs_dF_sampled": sampled_error(pthip, O, b3, f3, 200, model=1, u=ug)}
+        ckpt = os.path.join(ROOT, "paper_1504_07433_amd", "data", "surrogate.npz")
+        if os.path.exists(ckpt):
+            from paper_1504_07433_amd.surrogate import Surrogate
+            sur = Surrogate()
+            sur.load(ckpt)
+            frac = sur.install()
+            f3s = torch.empty(b3["n_flux"], dtype=torch.float32, device="cuda")
+            w3s, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="surrogate", out=f3s), 5, 1)
+            paths["ma_surrogate_spectrophotometric"] = {
+                "workload": b3["name"], "points_per_s": p3 * 5 / w3s, "ms_per_step": w3s / 5 * 1e3,
+                "trusted_cell_fraction": frac,
+                "max_abs_dF_sampled": sampled_error(pthip, O, b3, f3s, 300, seed=4)}
+            paths["surrogate_over_plain_fp32"] = (w3 / 10) / (w3s / 5)
+            paths["surrogate_over_plain_fp64_long_cadence_rate"] = (p3 * 5 / w3s) / paths["ma_fp64_same_workload"]["points_per_s"]
         line["paths"] = paths
 
     if not args.no_cpu:
