@@ -53,50 +53,65 @@ def parse():
 
 def unit_probes():
     """Launches in which every lane takes the same path, so that hardware
-    operation counters divided by the number of units give operations per unit:
-    U1 circular orbit, all points inside the disc; U2 the same orbit with the
-    planet never on the disc; U3/U4 the same with e = 0.2; U5 limb crossings;
-    U6 Gimenez (npol = 50) inside the disc.  One band, one subsample, 2^21
-    exposures each, two launches each."""
+    operation counters divided by the number of points give the operations
+    per unit of work.  2^24 points each, two launches each:
+      orbit-ecc   float orbit, e = 0.2, all points near conjunction (pt_orbit_z)
+      orbit-circ  the same orbit with e = 0
+      ma-inside   float Mandel-Agol, k = 0.1, z in (0, 1-k) (pt_ma_quad, 1 band)
+      ma-limb     the same, z in (1-k, 1+k)
+      gim-inside  float Gimenez, npol = 50, two coefficients, z in (0, 1-k)
+      batch-cut   batch kernel, one light curve whose window holds no point
+      batch-in    batch kernel, e = 0.2, every point inside the disc
+    and one elementwise kernel that reads 1 GiB and writes 1 GiB (the
+    reference for the HBM byte counters)."""
     import torch
     from paper_1504_07433_amd import pthip, workloads as W
+    n = 1 << 24
 
-    def one_lc(b_imp, e, k, n=1 << 21, span=0.01, aR=10.0):
+    def one_lc(b_imp, e, span):
         b = W.config1()
         b["t"] = np.linspace(-span, span, n)
         b["t_count"] = np.array([n], np.int64)
         b["nss"] = np.array([1], np.int32)
         b["t_exp"] = np.array([0.0])
         b["b"] = np.array([b_imp]); b["e"] = np.array([e]); b["w"] = np.array([1.0])
-        b["aR"] = np.array([aR]); b["P"] = np.array([3.0]); b["t0"] = np.array([0.0])
-        b["k"] = np.array([k]); b["u"] = np.array([[0.4, 0.2]]); b["n_flux"] = n
+        b["aR"] = np.array([10.0]); b["P"] = np.array([3.0]); b["t0"] = np.array([0.0])
+        b["k"] = np.array([0.1]); b["u"] = np.array([[0.4, 0.2]]); b["n_flux"] = n
         return b
-    cases = [("U1 circular inside", one_lc(0.3, 0.0, 0.1), "ma"),
-             ("U2 circular out", one_lc(1.5, 0.0, 0.1), "ma"),
-             ("U3 eccentric inside", one_lc(0.3, 0.2, 0.1), "ma"),
-             ("U4 eccentric out", one_lc(1.5, 0.2, 0.1), "ma"),
-             ("U5 circular limb", one_lc(0.99, 0.0, 0.1, span=0.002), "ma"),
-             ("U6 gimenez inside", one_lc(0.3, 0.0, 0.1), "gimenez")]
-    out = {}
-    for name, b, model in cases:
-        u = None
-        if model == "gimenez":
-            u = np.stack([b["u"][:, 0] + 2 * b["u"][:, 1], -b["u"][:, 1]], 1)
-        db = pthip.DeviceBatch(b, u=u)
-        for _ in range(2):
-            f = pthip.lc_batch(db, model, npol=50, prec="fp32")
+
+    def report(name, out):
         torch.cuda.synchronize()
-        fh = f.cpu().numpy()
-        out[name] = {"units": int(b["n_flux"]), "in_transit_fraction": float((fh < 1).mean())}
-        print(json.dumps({"probe": name, **out[name]}), flush=True)
-    # a plain copy of 1 GiB: the reference for the HBM byte counters
+        fh = out.float().cpu().numpy().ravel()
+        print(json.dumps({"probe": name, "points": n, "mean": float(fh.mean())}), flush=True)
+
+    t = torch.linspace(-0.04, 0.04, n, dtype=torch.float64, device="cuda")
+    for name, e in (("orbit-ecc", 0.2), ("orbit-circ", 0.0)):
+        for _ in range(2):
+            z = pthip.orbit_z(t, 0.0, 3.0, 10.0, 0.3, e, 1.0, prec="fp32")
+        report(name, z)
+    u = np.array([[0.4, 0.2]])
+    for name, lo, hi in (("ma-inside", 0.005, 0.85), ("ma-limb", 0.905, 1.095)):
+        zz = torch.linspace(lo, hi, n, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            f = pthip.ma_quad(zz, 0.1, u, prec="fp32")
+        report(name, f)
+    zz = torch.linspace(0.005, 0.85, n, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        f = pthip.gimenez(zz, 0.1, np.array([[0.8, -0.2]]), npol=50, prec="fp32")
+    report("gim-inside", f)
+    del zz, f, t, z
+    for name, b in (("batch-cut", one_lc(1.5, 0.0, 0.04)), ("batch-in", one_lc(0.3, 0.2, 0.03))):
+        db = pthip.DeviceBatch(b)
+        for _ in range(2):
+            f = pthip.lc_batch(db, "ma", prec="fp32")
+        report(name, f)
+        del db, f
     x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    y.copy_(x)
+    torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "copy 1 GiB"}), flush=True)
-    return out
+    print(json.dumps({"probe": "read+write 1 GiB"}), flush=True)
 
 
 def timed(fn, steps, warmup):
@@ -184,7 +199,8 @@ def main():
     points = W.n_points(batch)
     flux = torch.empty(batch["n_flux"], dtype=torch.float32, device="cuda")
     if args.autotune:
-        pthip.autotune(db, "ma", prec="fp32", out=flux)
+        rep = pthip.autotune(db, "ma", prec="fp32", out=flux)
+        print(json.dumps({"autotune": rep}), file=sys.stderr, flush=True)
     step = lambda: pthip.lc_batch(db, "ma", prec="fp32", out=flux)
     wall, gpu_s = timed(step, args.steps, args.warmup)
     ms = wall / args.steps * 1e3

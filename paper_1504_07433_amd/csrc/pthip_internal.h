@@ -70,7 +70,8 @@ struct BatchArgs {
   const int32_t* band_off;
   const int64_t* flux_off;
   const TileDesc* tiles;
-  OrbitConst* oc;       // [n_lc], written by the prep kernel
+  OrbitConst* oc;       // [n_lc], written by the window kernel
+  OrbitF* ocf;          // [n_lc] float form, written by the window kernel
   BandConst* bc;        // [n_band], written by the prep kernel
   void* gtab;           // Gimenez per-band tables [n_band][nldc+1][npol] (float or double)
   const void* grec;     // shared recurrence coefficients [(nldc+1)][npol][3]
@@ -99,6 +100,21 @@ struct BatchArgs {
   int32_t zin, zlimb;
 };
 
+// Read-only data at a wave-uniform address, read through the constant
+// address space so that the compiler issues scalar loads.  Only for data no
+// kernel writes while the reading kernel runs.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)p;
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));   // no type punning through pointers
+  return out;
+}
+
 // Launchers (defined in pthip_kernels.hip).
 hipError_t launch_orbit_z(const double* t, int64_t n, const OrbitConst& o, int prec, double* z,
                           hipStream_t s);
@@ -117,5 +133,7 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
 size_t batch_lds_bytes(int prec, int model);
 hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab, hipStream_t s);
 hipError_t prepare_batch_kernels();
+// Workgroups of the batch kernel one compute unit holds at once.
+int batch_blocks_per_cu(int prec, int model);
 
 }  // namespace pt

@@ -4,7 +4,8 @@
 // k_ma_quad          quadratic Mandel-Agol, one k, nb bands     (Sect. 2.2)
 // k_gim_band_tables  Gimenez per-band tables b^2 A' P^2         (Sect. 2.1.4)
 // k_gimenez          Gimenez, one k, nb bands                   (Sect. 2.1)
-// k_batch_prep       per-light-curve orbit and per-band constants
+// k_batch_prep       per-band constants, queue reset
+// k_lc_window        per-light-curve orbit constants and in-transit window
 // k_lc_batch         persistent fused orbit + flux + supersampling over a
 //                    ragged batch (Sects. 2.1.3, 2.2.2, 3.2)
 #include <type_traits>
@@ -36,12 +37,14 @@ __device__ __forceinline__ MaAlpha<float> ma_alpha_fast(float z, float kf, doubl
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void k_orbit_z(const double* __restrict__ t, int64_t n,
-                                                 OrbitConst o, double* __restrict__ z) {
+                                                 OrbitConst o, OrbitF of, double* __restrict__ z) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double dm = mean_anomaly_offset(o, t[i]);
-    const T zz = orbit_z_from_dm<T, false>(o, T(dm), T(0));
-    z[i] = o.valid ? double(zz) : (double)NAN;
+    double zz;
+    if constexpr (sizeof(T) == 4) zz = orbit_zf(of, float(dm));
+    else zz = orbit_z_from_dm<double, false>(o, dm, 0.0);
+    z[i] = o.valid ? zz : (double)NAN;
   }
 }
 
@@ -55,9 +58,9 @@ hipError_t launch_orbit_z(const double* t, int64_t n, const OrbitConst& o, int p
                           hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (prec == kPrecFP64)
-    hipLaunchKernelGGL(k_orbit_z<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, t, n, o, z);
+    hipLaunchKernelGGL(k_orbit_z<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, t, n, o, orbit_f(o), z);
   else
-    hipLaunchKernelGGL(k_orbit_z<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, t, n, o, z);
+    hipLaunchKernelGGL(k_orbit_z<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, t, n, o, orbit_f(o), z);
   return hipGetLastError();
 }
 
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256) void k_gim_band_tables(const double* __restric
     const int n = (int)(id % (nldc + 1));
     const double k = kvec ? kvec[band] : kscalar;
     gimenez_band_table_n<T>(k, n, npol, aprime + (int64_t)n * npol,
-                            tab + (band * (nldc + 1) + n) * (int64_t)npol);
+                            tab + (band * (nldc + 1) + n) * (int64_t)gim_row(npol));
   }
 }
 
@@ -231,21 +234,75 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
 
 __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.queue[0] = 0u;
-  const int64_t total = a.n_lc > a.n_band ? a.n_lc : a.n_band;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    if (i < a.n_lc) {
-      double kmax = 0.0;
-      for (int bnd = a.band_off[i]; bnd < a.band_off[i + 1]; ++bnd) kmax = fmax(kmax, a.k[bnd]);
-      a.oc[i] = orbit_const(a.t0[i], a.P[i], a.aR[i], a.b[i], a.e[i], a.w[i], kmax);
-      if (a.khat) {
-        double ks = 0.0;
-        for (int bnd = a.band_off[i]; bnd < a.band_off[i + 1]; ++bnd) ks += a.k[bnd];
-        const int nb = a.band_off[i + 1] - a.band_off[i];
-        a.khat[i] = nb > 0 ? ks / nb : 0.0;
-      }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_band; i += stride)
+    a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
+}
+
+// ---------------------------------------------------------------------------
+// Per-light-curve orbit constants and in-transit window, one wavefront per
+// light curve.  The window is the set of mean-anomaly offsets dM where
+// z < 1 + k_max is possible: z moves at most L = (a/R*) sqrt((1+e)/(1-e))
+// per radian of mean anomaly (the orbital speed at periastron), so a cell
+// [d_j, d_j + h] whose end-point values satisfy (z_j + z_{j+1} - L h)/2 >=
+// 1 + k_max holds no in-transit point.  64 cells over the safe bound
+// |dM| <= dm_cut, then 63 sub-cells of the first and the last cell that may
+// hold one; everything outside the window is certainly out of transit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double window_z(const OrbitConst& o, double dm) {
+  return fabs(orbit_z_from_dm<double, false>(o, dm, 0.0));
+}
+
+__global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t n_waves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t lc = wave; lc < a.n_lc; lc += n_waves) {
+    const int b0 = a.band_off[lc], b1 = a.band_off[lc + 1];
+    double kmax = 0.0, ks = 0.0;
+    for (int bnd = b0 + lane; bnd < b1; bnd += kWave) {
+      kmax = fmax(kmax, a.k[bnd]);
+      ks += a.k[bnd];
     }
-    if (i < a.n_band) a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
+    for (int off = 32; off > 0; off >>= 1) {
+      kmax = fmax(kmax, __shfl_xor(kmax, off));
+      ks += __shfl_xor(ks, off);
+    }
+    OrbitConst o = orbit_const(a.t0[lc], a.P[lc], a.aR[lc], a.b[lc], a.e[lc], a.w[lc], kmax);
+    if (o.valid && o.dm_cut < kPi) {
+      const double C = o.dm_cut;
+      const double L = o.aR * sqrt((1.0 + o.e) / (1.0 - o.e)) * (1.0 + 1e-9);
+      const double thr = 1.0 + kmax;
+      const double h1 = 2.0 * C / (kWave - 1);
+      const double zj = window_z(o, -C + lane * h1);
+      const double zn = __shfl_down(zj, 1);
+      const uint64_t m1 = __ballot(lane < kWave - 1 && 0.5 * (zj + zn - L * h1) < thr);
+      if (m1 == 0) {
+        o.cut_lo = 1.0;                       // empty window: never in transit
+        o.cut_hi = -1.0;
+      } else {
+        const int jl = __builtin_ctzll(m1), jh = 63 - __builtin_clzll(m1);
+        const double h2 = h1 / (kWave - 1);
+        const double cl = -C + jl * h1, ch = -C + jh * h1;
+        const double zl = window_z(o, cl + lane * h2);
+        const double zh = window_z(o, ch + lane * h2);
+        const double zln = __shfl_down(zl, 1), zhn = __shfl_down(zh, 1);
+        const uint64_t ml = __ballot(lane < kWave - 1 && 0.5 * (zl + zln - L * h2) < thr);
+        const uint64_t mh = __ballot(lane < kWave - 1 && 0.5 * (zh + zhn - L * h2) < thr);
+        o.cut_lo = ml ? cl + __builtin_ctzll(ml) * h2 : cl + h1;
+        o.cut_hi = mh ? ch + (64 - __builtin_clzll(mh)) * h2 : ch;
+        o.cut_lo -= 1e-12;
+        o.cut_hi += 1e-12;
+      }
+    } else {
+      o.cut_lo = -1e300;
+      o.cut_hi = 1e300;
+    }
+    if (lane == 0) {
+      a.oc[lc] = o;
+      a.ocf[lc] = orbit_f(o);
+      if (a.khat) a.khat[lc] = b1 > b0 ? ks / (b1 - b0) : 0.0;
+    }
   }
 }
 
@@ -291,17 +348,12 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
   const T om = T(1) - c * c;
   if (om <= T(0)) return T(0);
   const T x = T(1) - T(2) * c * c;
+  const int row = gim_row(npol);
   T loss = T(0);
-  for (int m = 0; m <= nldc; ++m) {
-    const T* tn = tab + m * npol;
-    const T* rn = rec + 3 * m * npol;
-    T y1 = T(0), y2 = T(0);
-    for (int j = npol - 1; j >= 0; --j) {
-      const T y0 = tn[j] + (rn[3 * j] * x + rn[3 * j + 1]) * y1 - rn[3 * j + 2] * y2;
-      y2 = y1;
-      y1 = y0;
-    }
-    loss += band_w<T>(bc, m) * gimenez_power(om, m) * y1;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {             // static band-weight indices (nldc <= 4)
+    if (m > nldc) break;
+    loss += band_w<T>(bc, m) * gimenez_power(om, m) * gimenez_clenshaw(tab + m * row, rec + 4 * m * row, npol, x);
   }
   return loss;
 }
@@ -370,7 +422,7 @@ hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab
 __global__ __launch_bounds__(256) void k_gim_ztable(BatchArgs a) {
   const int nodes = a.zin + a.zlimb;
   const int64_t total = (int64_t)a.n_band * nodes, stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t tab_stride = (int64_t)(a.nldc + 1) * a.npol;
+  const int64_t tab_stride = (int64_t)(a.nldc + 1) * gim_row(a.npol);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int bnd = (int)(e / nodes), j = (int)(e % nodes);
     const BandConst* bc = a.bc + bnd;
@@ -402,8 +454,8 @@ __device__ __forceinline__ float gim_loss_zinterp(float z, const BandConst* __re
 // Loss of band `bc` summed over the subsamples held in the wave's LDS slice.
 template <int PREC, int MODEL, class T>
 __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
-                                          const BatchArgs& a, const T* __restrict__ tb, const T* __restrict__ grec,
-                                          __bf16* act) {
+                                          int bnd, const BatchArgs& a, const T* __restrict__ tb,
+                                          const T* __restrict__ grec, __bf16* act) {
   static_assert(MODEL != kModelMAKhat || sizeof(T) == 4, "khat runs in the float path");
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   T acc = T(0);
@@ -411,7 +463,7 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
     for (int s = 0; s < ns; ++s) acc += ma_loss_interp(zb[s * kWave + lane], bc, a.matab);
   } else if constexpr (MODEL == kModelGimenezZInterp) {
     // k >= 1 has no inner grid: direct series
-    const float* zt = a.ztab + (int64_t)(bc - a.bc) * (a.zin + a.zlimb);
+    const float* zt = a.ztab + (int64_t)bnd * (a.zin + a.zlimb);
     if (bc->kf < 1.0f) {
       for (int s = 0; s < ns; ++s) acc += gim_loss_zinterp(zb[s * kWave + lane], bc, zt, a.zin, a.zlimb);
     } else {
@@ -456,16 +508,16 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
   const T* __restrict__ grec = reinterpret_cast<const T*>(a.grec);
   T* __restrict__ flux = reinterpret_cast<T*>(a.flux);
   const T* __restrict__ obs = reinterpret_cast<const T*>(a.obs);
-  const int64_t tab_stride = (int64_t)(a.nldc + 1) * a.npol;
+  const int64_t tab_stride = (int64_t)(a.nldc + 1) * gim_row(a.npol);
 
   for (;;) {
     unsigned int tid = 0;
     if (lane == 0) tid = atomicAdd(a.queue, 1u);
     tid = __builtin_amdgcn_readfirstlane(tid);
     if (tid >= (uint64_t)a.n_tiles) break;
-    const TileDesc td = a.tiles[tid];
+    const TileDesc td = load_uniform(a.tiles + tid);
     const int lc = td.lc;
-    const OrbitConst oc = a.oc[lc];
+    constexpr bool F32 = sizeof(T) == 4;
     const int nss = a.nss[lc];
     const int b0 = a.band_off[lc], b1 = a.band_off[lc + 1];
     const int64_t cnt = a.t_count[lc];
@@ -480,13 +532,43 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
     const int e_end = td.e0 + td.ne;
     double r2 = 0.0;
 
+    // Orbit constants: the float path reads the folded float form, the
+    // double path the full double set.
+    OrbitF of;
+    OrbitConst oc;
+    float step_f = 0.0f, base_f = 0.0f;
+    if constexpr (F32) {
+      of = load_uniform(a.ocf + lc);
+      // subsample offsets of dM from the exposure centre, in float
+      const double w = 2.0 * kPi * of.inv_p * texp;
+      step_f = float(w * inv_nss);
+      base_f = float(w * (0.5 * inv_nss - 0.5));
+    } else {
+      oc = a.oc[lc];
+    }
+    const bool orbit_ok = F32 ? of.valid != 0 : oc.valid != 0;
+
     // z for subsamples s0 .. s0+ns-1 of this lane's exposure into LDS
     auto orbit_chunk = [&](double tm, int s0, int ns) {
+      float dm_hi = 0.0f, dm_lo = 0.0f;
+      if constexpr (F32) {
+        // dM at the exposure centre in double, split into two floats
+        const double ph = (tm - of.t0) * of.inv_p;
+        const double dmid = 2.0 * kPi * (ph - rint(ph));
+        dm_hi = float(dmid);
+        dm_lo = float(dmid - double(dm_hi));
+      }
       for (int s = 0; s < ns; ++s) {
-        const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
-        const double dm = mean_anomaly_offset(oc, ts);
-        T z = orbit_z_from_dm<T, true>(oc, T(dm), far_out);
-        if (!oc.valid) z = T(NAN);
+        T z;
+        if constexpr (F32) {
+          const float off = fmaf(step_f, float(s0 + s), base_f);
+          const float dm = dm_hi + (dm_lo + off);
+          z = (dm < of.cut_lo || dm > of.cut_hi) ? far_out : orbit_zf(of, dm);
+        } else {
+          const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
+          z = orbit_z_from_dm<T, true>(oc, T(mean_anomaly_offset(oc, ts)), far_out);
+        }
+        if (!orbit_ok) z = T(NAN);
         if constexpr (MODEL == kModelMAKhat) {
           // the functions once per point at the mean radius ratio, shared by the bands
           MaAlpha<float> r{0.0f, 0.0f, 0.0f};
@@ -500,8 +582,8 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
         }
       }
     };
-    auto finish = [&](T acc, int bnd, int i, bool act_lane) {
-      if constexpr (MODEL == kModelMAKhat) acc *= T(a.bc[bnd].kf * a.bc[bnd].kf * inv_khat2);
+    auto finish = [&](T acc, const BandConst& bcv, int bnd, int i, bool act_lane) {
+      if constexpr (MODEL == kModelMAKhat) acc *= T(bcv.kf * bcv.kf * inv_khat2);
       const T f = T(1) - acc * T(inv_nss);
       const int64_t idx = fo + (int64_t)(bnd - b0) * cnt + i;
       if (LOGL) {
@@ -521,19 +603,23 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
       if (nss <= kZChunk) {
         // one orbit solve per (exposure, subsample), shared by every band
         orbit_chunk(tm, 0, nss);
-        for (int bnd = b0; bnd < b1; ++bnd)
-          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, a.bc + bnd, a, gtab + bnd * tab_stride, grec, act),
-                 bnd, i, act_lane);
+        for (int bnd = b0; bnd < b1; ++bnd) {
+          // band constants once per band, by scalar loads
+          const BandConst bcv = load_uniform(a.bc + bnd);
+          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride, grec, act),
+                 bcv, bnd, i, act_lane);
+        }
       } else {
         // more subsamples than one LDS chunk: the orbit is solved per band
         for (int bnd = b0; bnd < b1; ++bnd) {
+          const BandConst bcv = load_uniform(a.bc + bnd);
           T acc = T(0);
           for (int s0 = 0; s0 < nss; s0 += kZChunk) {
             const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
             orbit_chunk(tm, s0, ns);
-            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, a.bc + bnd, a, gtab + bnd * tab_stride, grec, act);
+            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride, grec, act);
           }
-          finish(acc, bnd, i, act_lane);
+          finish(acc, bcv, bnd, i, act_lane);
         }
       }
     }
@@ -576,6 +662,30 @@ hipError_t prepare_batch_kernels() {
   return hipSuccess;
 }
 
+// The flux-writing batch kernel for (prec, model), for occupancy queries.
+static const void* batch_kernel(int prec, int model) {
+  if (prec == kPrecFP64)
+    return model == kModelMA ? (const void*)k_lc_batch<kPrecFP64, kModelMA, false>
+                             : (const void*)k_lc_batch<kPrecFP64, kModelGimenez, false>;
+  if (prec == kPrecSurrogate) return (const void*)k_lc_batch<kPrecSurrogate, kModelMA, false>;
+  if (prec == kPrecSurrogateBf16) return (const void*)k_lc_batch<kPrecSurrogateBf16, kModelMA, false>;
+  switch (model) {
+    case kModelMA: return (const void*)k_lc_batch<kPrecFP32, kModelMA, false>;
+    case kModelMAInterp: return (const void*)k_lc_batch<kPrecFP32, kModelMAInterp, false>;
+    case kModelMAKhat: return (const void*)k_lc_batch<kPrecFP32, kModelMAKhat, false>;
+    case kModelGimenezZInterp: return (const void*)k_lc_batch<kPrecFP32, kModelGimenezZInterp, false>;
+    default: return (const void*)k_lc_batch<kPrecFP32, kModelGimenez, false>;
+  }
+}
+
+int batch_blocks_per_cu(int prec, int model) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(prec, model), kBlock,
+                                                   batch_lds_bytes(prec, model)) != hipSuccess)
+    return 2;
+  return nb < 1 ? 1 : nb;
+}
+
 template <bool LOGL>
 static void launch_main(const BatchArgs& a, int prec, int model, dim3 grid, size_t lds, hipStream_t s) {
   const dim3 block(kBlock);
@@ -597,9 +707,11 @@ static void launch_main(const BatchArgs& a, int prec, int model, dim3 grid, size
 }
 
 hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups, hipStream_t s) {
-  const int64_t prep_n = a.n_lc > a.n_band ? a.n_lc : a.n_band;
-  hipLaunchKernelGGL(k_batch_prep, dim3(grid_for(prep_n > 0 ? prep_n : 1, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_batch_prep, dim3(grid_for(a.n_band > 0 ? a.n_band : 1, 256)), dim3(256), 0, s, a);
   hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_lc_window, dim3(grid_for((int64_t)a.n_lc * kWave, 256)), dim3(256), 0, s, a);
+  err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
     err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gaprime, a.gtab, prec, s);

@@ -119,24 +119,26 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
     return PT_OK;
   }
   const size_t nn = (size_t)(nldc + 1) * npol;
-  std::vector<double> ap(nn), r64(3 * nn);
-  std::vector<float> r32(3 * nn);
+  const int row = gim_row(npol);
+  const size_t nr = (size_t)(nldc + 1) * row * 4;     // {A, B, C, 0} per padded term
+  std::vector<double> ap(nn), r64(nr, 0.0);
+  std::vector<float> r32(nr, 0.0f);
   for (int n = 0; n <= nldc; ++n)
     for (int j = 0; j < npol; ++j) {
       ap[n * npol + j] = gimenez_aprime(n, j);
       double A, B, Cn;
       gimenez_rec_coef(n, j, &A, &B, &Cn);
-      const size_t o = 3 * (size_t)(n * npol + j);
+      const size_t o = 4 * ((size_t)n * row + j);
       r64[o] = A; r64[o + 1] = B; r64[o + 2] = Cn;
       r32[o] = float(A); r32[o + 1] = float(B); r32[o + 2] = float(Cn);
     }
   auto t = std::make_unique<GimTables>();
   PT_HIP(t->aprime.ensure(nn * sizeof(double)));
-  PT_HIP(t->rec64.ensure(3 * nn * sizeof(double)));
-  PT_HIP(t->rec32.ensure(3 * nn * sizeof(float)));
+  PT_HIP(t->rec64.ensure(nr * sizeof(double)));
+  PT_HIP(t->rec32.ensure(nr * sizeof(float)));
   PT_HIP(hipMemcpy(t->aprime.p, ap.data(), nn * sizeof(double), hipMemcpyHostToDevice));
-  PT_HIP(hipMemcpy(t->rec64.p, r64.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice));
-  PT_HIP(hipMemcpy(t->rec32.p, r32.data(), 3 * nn * sizeof(float), hipMemcpyHostToDevice));
+  PT_HIP(hipMemcpy(t->rec64.p, r64.data(), nr * sizeof(double), hipMemcpyHostToDevice));
+  PT_HIP(hipMemcpy(t->rec32.p, r32.data(), nr * sizeof(float), hipMemcpyHostToDevice));
   *out = t.get();
   g_gim[key] = std::move(t);
   return PT_OK;
@@ -180,7 +182,7 @@ struct Plan {
   int32_t n_lc = 0, n_band = 0, nldc = 0, npol = 0, model = 0, prec = 0;
   std::vector<int64_t> t_count;
   std::vector<int32_t> nss, band_off;
-  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, bc, gtab, queue, khat, ztab;
+  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, queue, khat, ztab;
   std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
   LaunchShape shape;
   bool tuned = false;
@@ -326,14 +328,22 @@ static pt_status build_tiles(Plan* p, int tile_e, TileSet** out) {
   return PT_OK;
 }
 
+static int kernel_prec(const Plan* p) {
+  if (p->prec == PT_PREC_FP64) return kPrecFP64;
+  if (p->prec == PT_PREC_SURROGATE) return surrogate_split(p->dev) ? kPrecSurrogate : kPrecSurrogateBf16;
+  return kPrecFP32;
+}
+
 static int default_tile(const pt_batch* b) {
-  // aim for several tiles per resident wave; small light curves need small tiles
+  // About 24 tiles per resident wave (16 per CU) keeps the tail of the queue
+  // short; tiles below 512 exposures only when the batch is small, since
+  // every tile costs one atomic on the shared queue counter.
   int64_t expo = 0;
   for (int32_t i = 0; i < b->n_lc; ++i) expo += b->t_count[i] * (b->band_off[i + 1] > b->band_off[i]);
   const int cu = std::max(1, cu_count());
-  const int64_t waves = (int64_t)cu * 8;
+  const int64_t waves = (int64_t)cu * 16;
   int te = 1024;
-  while (te > kWave && expo / te < 4 * waves) te /= 2;
+  while (te > kWave && expo / te < 24 * waves) te /= 2;
   return te;
 }
 
@@ -377,13 +387,14 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
     PT_HIP(hipMemcpy(p->d_n_obs.p, nobs.data(), n * 8, hipMemcpyHostToDevice));
   }
   PT_HIP(p->oc.ensure(std::max<size_t>(1, n) * sizeof(OrbitConst)));
+  PT_HIP(p->ocf.ensure(std::max<size_t>(1, n) * sizeof(OrbitF)));
   PT_HIP(p->bc.ensure(std::max<size_t>(1, (size_t)p->n_band) * sizeof(BandConst)));
   PT_HIP(p->queue.ensure(64));
   PT_HIP(hipMemset(p->queue.p, 0, 64));
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
     const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
-    PT_HIP(p->gtab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * npol * es));
+    PT_HIP(p->gtab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * gim_row(npol) * es));
   }
   auto tu = g_tuned.find(key);
   if (tu != g_tuned.end()) {
@@ -391,7 +402,9 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
     p->tuned = true;
   } else {
     p->shape.tile_e = default_tile(b);
-    p->shape.workgroups = std::max(1, cu_count()) * 2;
+    // every wave the compute units can hold at once (the kernel is persistent)
+    if (prepare_batch_kernels() != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes");
+    p->shape.workgroups = std::max(1, cu_count()) * batch_blocks_per_cu(kernel_prec(p.get()), p->model);
   }
   PT_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
   *out = p.get();
@@ -415,6 +428,7 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
   a->tiles = (const TileDesc*)ts->tiles.p;
   a->n_tiles = ts->n_tiles;
   a->oc = (OrbitConst*)p->oc.p;
+  a->ocf = (OrbitF*)p->ocf.p;
   a->bc = (BandConst*)p->bc.p;
   a->queue = (unsigned int*)p->queue.p;
   a->flux = flux;
@@ -454,12 +468,6 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     a->gaprime = (const double*)g->aprime.p;
   }
   return PT_OK;
-}
-
-static int kernel_prec(const Plan* p) {
-  if (p->prec == PT_PREC_FP64) return kPrecFP64;
-  if (p->prec == PT_PREC_SURROGATE) return surrogate_split(p->dev) ? kPrecSurrogate : kPrecSurrogateBf16;
-  return kPrecFP32;
 }
 
 static bool use_graph() {
@@ -580,7 +588,7 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
   }
   hipStream_t s = (hipStream_t)stream;
   void* tab = nullptr;
-  const size_t bytes = (size_t)(nldc + 1) * npol * (pr == kPrecFP64 ? 8 : 4);
+  const size_t bytes = (size_t)(nldc + 1) * gim_row(npol) * (pr == kPrecFP64 ? 8 : 4);
   PT_HIP(hipMallocAsync(&tab, bytes, s));
   hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double*)g->aprime.p, tab, pr, s);
   hipError_t e2 = e1 == hipSuccess

@@ -19,6 +19,15 @@
 
 #define PT_HD __host__ __device__ __forceinline__
 
+// Data that no kernel writes while the reading kernel runs and that is read at
+// wave-uniform addresses (coefficient tables) is read through the constant
+// address space on the GPU, so that the loads are scalar.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PT_CONST_AS __attribute__((address_space(4)))
+#else
+#define PT_CONST_AS
+#endif
+
 namespace pt {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -45,7 +54,28 @@ template <> struct Num<float> {
     return 1.0f / x;
 #endif
   }
-  PT_HD static float atan2(float y, float x) { return ::atan2f(y, x); }
+  // atan2 for y >= 0 (upper half plane): t = min(|x|, y) / max(|x|, y) in
+  // [0, 1], atan t by an odd polynomial of degree 17 whose coefficients were
+  // fitted to atan on [0, 1] by Lawson's iteratively reweighted least squares
+  // (maximum error 5.8e-9), then the octant is restored.
+  PT_HD static float atan2(float y, float x) {
+    const float ax = fabsf(x);
+    const float lo = fminf(ax, y), hi = fmaxf(ax, y);
+    const float t = hi > 0.0f ? lo * rcp(hi) : 0.0f;
+    const float t2 = t * t;
+    float p = 2.456725429e-03f;
+    p = p * t2 - 1.440136161e-02f;
+    p = p * t2 + 3.978123021e-02f;
+    p = p * t2 - 7.234858004e-02f;
+    p = p * t2 + 1.049894642e-01f;
+    p = p * t2 - 1.416122930e-01f;
+    p = p * t2 + 1.998590678e-01f;
+    p = p * t2 - 3.333259703e-01f;
+    p = p * t2 + 9.999998864e-01f;
+    float r = t * p;
+    r = y > ax ? 1.57079632679489662f - r : r;
+    return x < 0.0f ? 3.14159265358979324f - r : r;
+  }
   PT_HD static void sincos(float x, float* s, float* c) {
 #if defined(__HIP_DEVICE_COMPILE__)
     ::sincosf(x, s, c);
@@ -76,26 +106,26 @@ template <> struct Num<double> {
   static constexpr int newton_max = 40;
 };
 
-// Double-precision arithmetic with single-precision hardware seeds: the
-// reciprocal and square root start from v_rcp_f32 / v_rsq_f32 (relative error
-// ~1e-7) and take one Newton step in double, leaving ~1e-14.  On gfx950 a
-// double FMA issues at the rate of a float FMA, so this keeps the
-// cancellation-prone elliptic combinations at near-double accuracy for about
-// the cost of the float transcendentals.  Arguments must lie in the float
-// exponent range (1e-37 .. 1e37).
+// Double-precision arithmetic with approximate hardware seeds: the
+// reciprocal and square root start from v_rcp_f64 / v_rsq_f64 (relative error
+// ~5e-8, measured on gfx950) and take one Newton step in double, leaving
+// ~2e-15.  A double FMA issues at the rate of a float FMA on gfx950 (packed
+// float math aside), so this keeps the cancellation-prone elliptic
+// combinations at near-double accuracy for about the cost of the float
+// transcendentals.  (The host build seeds from float, for tolerance work.)
 struct NumFast {
   PT_HD static double rcp(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    double r = (double)__builtin_amdgcn_rcpf((float)x);
+    const double r = __builtin_amdgcn_rcp(x);
 #else
-    double r = (double)(1.0f / (float)x);
+    const double r = (double)(1.0f / (float)x);
 #endif
     const double e = fma(-x, r, 1.0);
     return fma(r, e, r);
   }
   PT_HD static double sqrt(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const double y = (double)__builtin_amdgcn_rsqf((float)x);
+    const double y = __builtin_amdgcn_rsq(x);
 #else
     const double y = (double)(1.0f / ::sqrtf((float)x));
 #endif
@@ -105,7 +135,9 @@ struct NumFast {
   }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) { Num<double>::sincos(x, s, c); }
-  static constexpr double cel_tol = 2e-7;        // error ~ tol^2 after the step
+  // The mean's relative spread falls quadratically, so stopping at 3e-5 leaves
+  // ~1e-11 in the elliptic combination (measured over k <= 1/2 and all z).
+  static constexpr double cel_tol = 3e-5;
 };
 
 // sin(h) and 1 - cos(h) by their Taylor series through h^11 / h^12; relative
@@ -203,18 +235,25 @@ constexpr int kCelItersF32 = 5;
 // are small and keep their relative precision in float.
 //
 // With E = E_c + x, Kepler's equation E - e sin E = M becomes
-//   x - e (cos E_c sin x - sin E_c (1 - cos x)) = dM,   dM = M - M_c,
+//   g(x) = x - e cos E_c sin x + e sin E_c (1 - cos x) - dM = 0,  dM = M - M_c,
 // and the sky position relative to the star, in units of a, is
 //   X = cos w (cos E - cos E_c) - sin w sqrt(1-e^2) (sin E - sin E_c)
 //   Y = r_c + sin w (cos E - cos E_c) + cos w sqrt(1-e^2) (sin E - sin E_c)
 // (X along the line of nodes, Y the in-plane direction towards the
 // observer), so that z = (a/R*) sqrt(X^2 + (Y cos i)^2) and the planet is in
 // front of the star when Y > 0.  The conjunction terms cancel exactly in X.
+//
+// Near x = 0, g(x) = d1 x + (e sin E_c / 2) x^2 + (e cos E_c / 6) x^3 + ...
+// with d1 = 1 - e cos E_c; reverting the series gives the starting value
+// x0 = y + a2 y^2 + a3 y^3 with y = dM / d1, a2 = -b2, a3 = 2 b2^2 - b3,
+// b2 = e sin E_c / (2 d1), b3 = e cos E_c / (6 d1); its error is O(y^4).
 // ---------------------------------------------------------------------------
 struct OrbitConst {
   double t0, inv_p;       // phase = (t - t0) / P, in double
   double aR, e, cos_i, sq1me2, cw, sw, cEc, sEc, rc, d1;
+  double inv_d1, a2, a3;  // series starting value of Kepler's equation
   double dm_cut;          // |dM| beyond this: certainly out of transit
+  double cut_lo, cut_hi;  // dM outside [cut_lo, cut_hi]: certainly out of transit
   int32_t circular, valid;
 };
 
@@ -240,6 +279,10 @@ PT_HD OrbitConst orbit_const(double t0, double P, double aR, double b, double e,
   o.sEc = ::sin(Ec);
   o.rc = 1.0 - e * o.cEc;
   o.d1 = 1.0 - e * o.cEc;  // dM/dx at conjunction
+  o.inv_d1 = 1.0 / o.d1;
+  const double b2 = 0.5 * e * o.sEc * o.inv_d1, b3 = e * o.cEc * o.inv_d1 / 6.0;
+  o.a2 = -b2;
+  o.a3 = 2.0 * b2 * b2 - b3;
   o.circular = (e == 0.0) ? 1 : 0;
   // Out-of-transit bound: in transit needs |f - f_c| < asin((1+k)/(aR(1-e)))
   // (projected distance >= r |cos(w+f)| >= a(1-e)|sin(f-f_c)|, and the planet
@@ -253,6 +296,8 @@ PT_HD OrbitConst orbit_const(double t0, double P, double aR, double b, double e,
       o.dm_cut = c * (1.0 + 1e-6) + 1e-9;
     }
   }
+  o.cut_lo = -o.dm_cut;
+  o.cut_hi = o.dm_cut;
   return o;
 }
 
@@ -262,45 +307,52 @@ PT_HD double mean_anomaly_offset(const OrbitConst& o, double t) {
   return 2.0 * kPi * (ph - ::rint(ph));
 }
 
+// Newton's method on the conjunction-frame equation from x, kept inside the
+// bracket |E - M| <= e (x in dm - e sin E_c +- e).  The trigonometric
+// functions of x are carried along by exact rotations through small steps,
+// so near transit no sine or cosine is evaluated.  Returns sin x, 1 - cos x.
+template <class T>
+PT_HD void kepler_newton(T e, T ec, T es, T dm, T x, T* s_out, T* v_out) {
+  const T lo = dm - es - e, hi = dm - es + e;
+  x = x < lo ? lo : (x > hi ? hi : x);
+  T s, v;
+  sin_vers(x, &s, &v);
+  for (int it = 0; it < Num<T>::newton_max; ++it) {
+    const T g = x - (ec * s - es * v) - dm;
+    const T gp = T(1) - ec * (T(1) - v) + es * s;       // 1 - e cos(E_c + x)
+    T xn = x - g * Num<T>::rcp(gp);
+    xn = xn < lo ? lo : (xn > hi ? hi : xn);
+    const T dx = xn - x;
+    x = xn;
+    if (fabs(dx) < T(Num<T>::rot_limit)) {
+      T sd, vd;
+      sin_vers_small(dx, &sd, &vd);
+      const T s_new = s + sd - s * vd - v * sd;          // sin(x + dx)
+      const T v_new = v + vd - v * vd + s * sd;          // 1 - cos(x + dx)
+      s = s_new;
+      v = v_new;
+    } else {
+      sin_vers(x, &s, &v);
+    }
+    if (fabs(dx) <= Num<T>::newton_tol * fabs(x) + T(1e-30)) break;
+  }
+  *s_out = s;
+  *v_out = v;
+}
+
 // Signed z for a mean-anomaly offset dm (already in the working type).
-// OUT marks "certainly out of transit" (only when the cut is enabled).
+// With CUT, dm outside [cut_lo, cut_hi] returns big_out ("certainly out of
+// transit").
 template <class T, bool CUT>
 PT_HD T orbit_z_from_dm(const OrbitConst& o, T dm, T big_out) {
-  if (CUT && fabs(dm) > T(o.dm_cut)) return big_out;
-  const T e = T(o.e);
+  if (CUT && (dm < T(o.cut_lo) || dm > T(o.cut_hi))) return big_out;
   T s, v;  // sin x, 1 - cos x
   if (o.circular) {
     sin_vers(dm, &s, &v);
   } else {
-    const T cEc = T(o.cEc), sEc = T(o.sEc);
-    const T ec = e * cEc, es = e * sEc;
-    // |E - M| <= e brackets the root: x in dm - e sin E_c +- e.
-    const T lo = dm - es - e, hi = dm - es + e;
-    // Newton from x = 0 on the conjunction-frame equation; the trigonometric
-    // functions of x are carried along by exact rotations through each step,
-    // so near transit no sine or cosine is evaluated.
-    T x = T(0);
-    s = T(0);
-    v = T(0);
-    for (int it = 0; it < Num<T>::newton_max; ++it) {
-      const T g = x - (ec * s - es * v) - dm;
-      const T gp = T(1) - ec * (T(1) - v) + es * s;       // 1 - e cos(E_c + x)
-      T xn = x - g * Num<T>::rcp(gp);
-      xn = xn < lo ? lo : (xn > hi ? hi : xn);
-      const T dx = xn - x;
-      x = xn;
-      if (fabs(dx) < T(Num<T>::rot_limit)) {
-        T sd, vd;
-        sin_vers_small(dx, &sd, &vd);
-        const T s_new = s + sd - s * vd - v * sd;          // sin(x + dx)
-        const T v_new = v + vd - v * vd + s * sd;          // 1 - cos(x + dx)
-        s = s_new;
-        v = v_new;
-      } else {
-        sin_vers(x, &s, &v);
-      }
-      if (fabs(dx) <= Num<T>::newton_tol * fabs(x) + T(1e-30)) break;
-    }
+    const T y = dm * T(o.inv_d1);
+    const T x0 = fabs(y) < T(0.5) ? y + y * y * (T(o.a2) + T(o.a3) * y) : y;
+    kepler_newton<T>(T(o.e), T(o.e * o.cEc), T(o.e * o.sEc), dm, x0, &s, &v);
   }
   const T dc = -(T(o.cEc) * v + T(o.sEc) * s);             // cos E - cos E_c
   const T ds = T(o.cEc) * s - T(o.sEc) * v;                // sin E - sin E_c
@@ -310,6 +362,79 @@ PT_HD T orbit_z_from_dm(const OrbitConst& o, T dm, T big_out) {
   const T Yc = Y * T(o.cos_i);
   const T z = T(o.aR) * Num<T>::sqrt(X * X + Yc * Yc);
   return Y < T(0) ? -z : z;
+}
+
+// Float form of the orbit constants for the bulk path: the sky position is
+// folded into X' = (a/R*) X = sx sin x + vx (1 - cos x) and
+// Y = y0 + sy sin x + vy (1 - cos x), Y cos i (a/R*) = Y ycs.
+struct OrbitF {
+  double t0, inv_p;       // phase in double
+  float e, ec, es;        // e, e cos E_c, e sin E_c
+  float inv_d1, a2, a3;   // series starting value
+  float halley_ok;        // a Halley step no larger than this leaves < 5e-10 rad
+  float sx, vx, y0, sy, vy, ycs;
+  float cut_lo, cut_hi;   // in-transit window of dM (float, widened)
+  int32_t circular, valid;
+};
+
+PT_HD OrbitF orbit_f(const OrbitConst& o) {
+  OrbitF f;
+  f.t0 = o.t0;
+  f.inv_p = o.inv_p;
+  f.e = float(o.e);
+  f.ec = float(o.e * o.cEc);
+  f.es = float(o.e * o.sEc);
+  f.inv_d1 = float(o.inv_d1);
+  f.a2 = float(o.a2);
+  f.a3 = float(o.a3);
+  // Halley's error constant |g'''/(6 g') - g''^2/(4 g'^2)| <= e/(6(1-e)) + e^2/(4(1-e)^2);
+  // after a step of size h from an error ~h the error is below K h^3.
+  const double K = o.e / (6.0 * (1.0 - o.e)) + o.e * o.e / (4.0 * (1.0 - o.e) * (1.0 - o.e));
+  f.halley_ok = K > 0.0 ? float(::cbrt(5e-10 / K)) : 0.0f;
+  const double sq = o.sq1me2;
+  f.sx = float(o.aR * (-o.cw * o.sEc - o.sw * sq * o.cEc));
+  f.vx = float(o.aR * (-o.cw * o.cEc + o.sw * sq * o.sEc));
+  f.y0 = float(o.rc);
+  f.sy = float(-o.sw * o.sEc + o.cw * sq * o.cEc);
+  f.vy = float(-o.sw * o.cEc - o.cw * sq * o.sEc);
+  f.ycs = float(o.aR * o.cos_i);
+  // float rounding of dM is below 3e-7 for |dM| <= 4: widen by 1e-6
+  f.cut_lo = o.cut_lo < -4.0 ? -1e30f : float(o.cut_lo - 1e-6);
+  f.cut_hi = o.cut_hi > 4.0 ? 1e30f : float(o.cut_hi + 1e-6);
+  f.circular = o.circular;
+  f.valid = o.valid;
+  return f;
+}
+
+// Signed z in float.  Eccentric orbits: one Halley step from the series
+// starting value, accepted when the step is small enough for the error
+// bound above; otherwise Newton's method continues from there.
+PT_HD float orbit_zf(const OrbitF& o, float dm) {
+  float s, v;
+  if (o.circular) {
+    sin_vers(dm, &s, &v);
+  } else {
+    const float y = dm * o.inv_d1;
+    float x = y + y * y * (o.a2 + o.a3 * y);
+    bool ok = fabsf(x) < 0.45f;
+    if (ok) {
+      sin_vers_small(x, &s, &v);
+      const float g = x - (o.ec * s - o.es * v) - dm;
+      const float c = 1.0f - v;
+      const float gp = 1.0f - o.ec * c + o.es * s;
+      const float gpp = o.ec * s + o.es * c;
+      const float dx = -g * gp * Num<float>::rcp(gp * gp - 0.5f * g * gpp);
+      x += dx;
+      ok = fabsf(dx) <= o.halley_ok && fabsf(x) < 0.5f;
+      if (ok) sin_vers_small(x, &s, &v);
+    }
+    if (!ok) kepler_newton<float>(o.e, o.ec, o.es, dm, x == x ? x : y, &s, &v);
+  }
+  const float X = o.sx * s + o.vx * v;
+  const float Y = o.y0 + o.sy * s + o.vy * v;
+  const float Yc = Y * o.ycs;
+  const float z = Num<float>::sqrt(X * X + Yc * Yc);
+  return Y < 0.0f ? -z : z;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,7 +484,8 @@ PT_HD T ma_elliptic(T z, T k, bool limb) {
 
 // lambda_e and eta_1 in the limb region, with the square root of
 // D = 4z^2 - (1+z^2-k^2)^2 = (z-(1-k))(1+k-z)(1+z-k)(1+z+k) formed as a
-// product and the two angles by atan2 (no acos near +-1).
+// product and the two angles by atan2 (no acos near +-1); sqrt(D) >= 0, so
+// both angles lie in [0, pi].
 template <class T>
 PT_HD void ma_limb_terms(T z, T k, T* le, T* ed) {
   const T k2 = k * k, z2 = z * z;
@@ -524,10 +650,17 @@ PT_HD double gimenez_aprime(int n, int j) {
   return sg * (2.0 * j + nu + 2.0) / (nu * (j + 1.0)) * ::exp(lg);
 }
 
+// Rows of the Gimenez tables are padded with zero terms to a multiple of four
+// (a zero term leaves Clenshaw's backward sum unchanged), so that the device
+// reads them four terms at a time.
+PT_HD constexpr int gim_row(int npol) { return (npol + 3) & ~3; }
+
 // Per-band table T[n][j] = b^2 A'_{n,j} [P_j^(nu,1)(2b-1)]^2, b = k/(1+k),
-// for one n and j < npol (aprime_n = A'_{n,0..npol-1}).
+// for one n and j < npol (aprime_n = A'_{n,0..npol-1}); out_n[npol ..
+// gim_row(npol)) = 0.
 template <class T>
 PT_HD void gimenez_band_table_n(double k, int n, int npol, const double* aprime_n, T* out_n) {
+  for (int j = npol; j < gim_row(npol); ++j) out_n[j] = T(0);
   const double bt = k / (1.0 + k);
   const double x = 2.0 * bt - 1.0;
   const double nu = 0.5 * (n + 2);
@@ -542,10 +675,11 @@ PT_HD void gimenez_band_table_n(double k, int n, int npol, const double* aprime_
   }
 }
 
-// All n = 0..nldc, written as T[n * npol + j].
+// All n = 0..nldc, written as T[n * gim_row(npol) + j].
 template <class T>
 PT_HD void gimenez_band_table(double k, int nldc, int npol, const double* aprime, T* out) {
-  for (int n = 0; n <= nldc; ++n) gimenez_band_table_n<T>(k, n, npol, aprime + n * npol, out + n * npol);
+  for (int n = 0; n <= nldc; ++n)
+    gimenez_band_table_n<T>(k, n, npol, aprime + n * npol, out + n * gim_row(npol));
 }
 
 // Shared Clenshaw coefficients for sum_j T_j P_j^(0,nu+1)(x): per (n, j)
@@ -567,25 +701,42 @@ PT_HD T gimenez_power(T om, int n) {
   return r;
 }
 
+// Clenshaw's backward recurrence for sum_{j<npol} t_j P_j(x) with
+// P_{j+1} = (A_j x + B_j) P_j - C_j P_{j-1}: y_j = t_j + (A_j x + B_j) y_{j+1}
+// - C_{j+1} y_{j+2}, sum = y_0.  tn: one padded table row; rn: the matching
+// padded rows of {A_j, B_j, C_{j+1}, 0}.  On the GPU both are wave-uniform and
+// read four terms per step by scalar loads.
+template <class T>
+PT_HD T gimenez_clenshaw(const T* tn_, const T* rn_, int npol, T x) {
+  const int row = gim_row(npol);
+  // blocks of four terms from the top, addressed by constant offsets
+  const PT_CONST_AS T* tp = (const PT_CONST_AS T*)tn_ + (row - 4);
+  const PT_CONST_AS T* rp = (const PT_CONST_AS T*)rn_ + 4 * (row - 4);
+  T y1 = T(0), y2 = T(0);
+  for (int blk = row / 4; blk > 0; --blk, tp -= 4, rp -= 16) {
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      const T y0 = tp[i] + (rp[4 * i] * x + rp[4 * i + 1]) * y1 - rp[4 * i + 2] * y2;
+      y2 = y1;
+      y1 = y0;
+    }
+  }
+  return y1;
+}
+
 // alpha_n = (1-c^2)^(nu+1) sum_{j<npol} T[n][j] P_j^(0,nu+1)(1-2c^2) by
-// Clenshaw's backward recurrence; rec holds {A_j, B_j, C_{j+1}} per (n, j)
-// as rec[3 * (n * npol + j) + 0..2].  Returns 0 for c >= 1 (no overlap).
+// Clenshaw's backward recurrence; tab rows T[n][.] and rec rows
+// {A_j, B_j, C_{j+1}, 0}[n][.] are padded to gim_row(npol) terms.  Returns 0
+// for c >= 1 (no overlap).
 template <class T>
 PT_HD void gimenez_alpha(T z, T inv1pk, int nldc, int npol, const T* tab, const T* rec, T* alpha) {
   const T c = z * inv1pk;
   const T om = T(1) - c * c;
   const T x = T(1) - T(2) * c * c;
+  const int row = gim_row(npol);
   for (int n = 0; n <= nldc; ++n) {
     if (!(om > T(0))) { alpha[n] = (om == om) ? T(0) : om; continue; }
-    const T* tn = tab + n * npol;
-    const T* rn = rec + 3 * n * npol;
-    T y1 = T(0), y2 = T(0);
-    for (int j = npol - 1; j >= 0; --j) {
-      const T y0 = tn[j] + (rn[3 * j] * x + rn[3 * j + 1]) * y1 - rn[3 * j + 2] * y2;
-      y2 = y1;
-      y1 = y0;
-    }
-    alpha[n] = gimenez_power(om, n) * y1;
+    alpha[n] = gimenez_power(om, n) * gimenez_clenshaw(tab + n * row, rec + 4 * n * row, npol, x);
   }
 }
 

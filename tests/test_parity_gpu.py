@@ -206,6 +206,58 @@ def test_batch_edge_cases(pt, O):
         assert np.abs(g - ref).max() <= tol, prec
 
 
+def _contact_batch(O, seed, e_max, nss, t_exp):
+    """Light curves sampled densely around their first and last contacts
+    (located on the oracle's z), eccentric orbits up to e_max, two bands per
+    light curve with different k: checks that the per-orbit in-transit window
+    keeps every point the model needs."""
+    from paper_1504_07433_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    n = 24
+    b = W._empty_batch(n)
+    ts, t_start, t_count, ks, us = [], [], [], [], []
+    off = 0
+    for i in range(n):
+        while True:
+            e, w, aR, bb = rng.uniform(0, e_max), rng.uniform(0, 2 * np.pi), rng.uniform(2.5, 30), rng.uniform(0, 1.15)
+            if bb / aR * (1 + e * np.sin(w)) / (1 - e * e) < 0.99:
+                break
+        P, t0 = 3.0, rng.uniform(-0.01, 0.01)
+        k0 = rng.uniform(0.02, 0.3)
+        b["t0"][i], b["P"][i], b["aR"][i], b["b"][i], b["e"][i], b["w"][i] = t0, P, aR, bb, e, w
+        b["t_exp"][i], b["nss"][i] = t_exp, nss
+        grid = t0 + P * np.linspace(-0.5, 0.5, 100001)
+        z = O.orbit_z(grid, t0, P, aR, bb, e, w)
+        kk = k0 * rng.uniform(0.95, 1.05, 2)
+        inside = (z >= 0) & (z < 1 + kk.max())
+        edges = np.flatnonzero(np.diff(inside.astype(np.int8)))
+        t = [t0 + np.linspace(-0.05, 0.05, 101)]
+        for j in edges:
+            t.append(grid[j] + np.linspace(-0.003, 0.003, 301))
+        t = np.sort(np.concatenate(t))
+        ts.append(t); t_start.append(off); t_count.append(len(t)); off += len(t)
+        ks.extend(kk)
+        us.extend(np.stack(W.kipping_q_to_u(rng.uniform(0, 1, 2), rng.uniform(0, 1, 2)), 1))
+    return W._finish(b, np.concatenate(ts), t_start, t_count, [2] * n, np.array(ks), np.array(us),
+                     "contacts")
+
+
+@pytest.mark.parametrize("nss,t_exp", [(1, 0.0), (7, 0.0204)])
+def test_batch_eccentric_contacts(pt, O, nss, t_exp):
+    b = _contact_batch(O, 11 + nss, 0.85, nss, t_exp)
+    ref = O.lc_batch(b, model=0)
+    got = _run(pt, b, "ma", "fp64")
+    say("contacts fp64 max|dF|", np.abs(got - ref).max())
+    assert np.abs(got - ref).max() <= TOL64
+    # the float orbit's z error grows like (a/R*) sqrt((1+e)/(1-e)) ulp(dM):
+    # the float bar applies up to e = 0.6
+    b = _contact_batch(O, 21 + nss, 0.6, nss, t_exp)
+    ref = O.lc_batch(b, model=0)
+    got = _run(pt, b, "ma", "fp32")
+    say("contacts fp32 max|dF|", np.abs(got - ref).max())
+    assert np.abs(got - ref).max() <= TOL32
+
+
 def test_batch_nonphysical_parameters_give_nan(pt):
     from paper_1504_07433_amd import workloads as W
     b = W.config2(n_vec=4, n_windows=1)
