@@ -24,16 +24,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit, counted from the arithmetic of the path (FMA = 2
-# flops, add/mul/compare-free ops = 1, each square root, reciprocal and
-# trigonometric call = 1); see the flop-count notes in the design document.
-FLOP_ORBIT = 110          # per (exposure, subsample): phase, Newton solve, z
-FLOP_MA_IN = 330          # per (band, exposure, subsample) with z < 1 + k
-FLOP_MA_OUT = 3           # per (band, exposure, subsample) out of transit
-FLOP_GIM_TERM = 6         # per Clenshaw term (3 FMA) per alpha_n
-FLOP_GIM_POINT = 20       # per in-transit point: c, powers, combination
-PEAK_ALU = 78.6e12        # FP32/FP64 non-packed VALU FMA peak (see design notes)
+# Algorithmic work per unit of the float path, in flops (FMA = 2, every other
+# arithmetic instruction and each reciprocal / square root = 1), counted with
+# the hardware flop counters on launches in which every lane does the same
+# unit of work (bench.py --mode units; summary and command in
+# profiles/unit_probes_flops.txt):
+F_ORBIT_ECC = 86.0        # orbit of one in-transit point, e > 0: Kepler, z (float part)
+F_MA_INSIDE = 277.7       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 377.3         # the same, 1 - k < z < 1 + k
+# Every point also pays the subsample offset of the mean anomaly and the
+# accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8).
+F_POINT, F_EXPOSURE = 5.0, 8.0
+PEAK_ALU = 78.6e12        # 256 CU x 64 FMA lanes x 2 flops x 2.4 GHz (FP32 non-packed = FP64)
+PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second
 HBM_PEAK = 8.0e12
+# From the counter runs of k_lc_batch<fp32, MA> on this workload
+# (profiles/k_lc_batch_fp32_ma_long_cadence_counters.txt): wave64 VALU
+# instructions per launch, and HBM bytes per launch from FETCH_SIZE and
+# WRITE_SIZE (KiB) scaled by what the counters read for an elementwise kernel
+# that reads and writes 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
+VALU_INSTS_PER_LAUNCH = None
+FETCH_KIB, WRITE_KIB = None, None
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
 def parse():
@@ -131,11 +143,12 @@ def timed(fn, steps, warmup):
 
 
 def count_units(pt, batch):
-    """Orbit points and in-transit (band, exposure, subsample) points, from
-    z on the GPU (pt_orbit_z per light curve over its subsample times)."""
+    """Units of work of one launch, from z on the GPU (pt_orbit_z in FP64 per
+    light curve over its subsample times): all orbit points, orbit points in
+    transit for some band, and in-transit (band, point) pairs inside the disc
+    and on the limb."""
     import torch
-    n_orbit = 0
-    n_in = 0
+    n_orbit = n_orbit_in = n_inside = n_limb = 0
     for i in range(len(batch["t_start"])):
         s, c, n = batch["t_start"][i], batch["t_count"][i], int(batch["nss"][i])
         t = torch.as_tensor(batch["t"][s:s + c], device="cuda")
@@ -144,10 +157,14 @@ def count_units(pt, batch):
         z = pt.orbit_z(ts, batch["t0"][i], batch["P"][i], batch["aR"][i], batch["b"][i],
                        batch["e"][i], batch["w"][i], prec="fp64")
         n_orbit += ts.numel()
-        for bnd in range(batch["band_off"][i], batch["band_off"][i + 1]):
-            k = float(batch["k"][bnd])
-            n_in += int(((z >= 0) & (z < 1 + k)).sum().item())
-    return n_orbit, n_in
+        ks = batch["k"][batch["band_off"][i]:batch["band_off"][i + 1]]
+        n_orbit_in += int(((z >= 0) & (z < 1 + float(ks.max()))).sum().item())
+        for k in ks:
+            k = float(k)
+            n_inside += int(((z >= 0) & (z <= 1 - k)).sum().item())
+            n_limb += int(((z > 1 - k) & (z < 1 + k)).sum().item())
+    return {"orbit_points": n_orbit, "orbit_points_in_transit": n_orbit_in,
+            "inside_points": n_inside, "limb_points": n_limb}
 
 
 def cpu_baseline(batch, seconds):
@@ -211,11 +228,24 @@ def main():
         print(json.dumps({"mode": "kernel", "ms_per_step": ms, "points_per_s": value}), flush=True)
         return
 
-    n_orbit, n_in = count_units(pthip, batch)
-    n_out = points - n_in
-    flops = n_orbit * FLOP_ORBIT + n_in * FLOP_MA_IN + n_out * FLOP_MA_OUT
+    u = count_units(pthip, batch)
+    n_in = u["inside_points"] + u["limb_points"]
+    n_exposures = int(batch["t_count"].sum())
+    flops = (u["orbit_points"] * F_POINT + n_exposures * F_EXPOSURE
+             + u["orbit_points_in_transit"] * F_ORBIT_ECC
+             + u["inside_points"] * F_MA_INSIDE + u["limb_points"] * F_MA_LIMB)
     achieved = flops / kernel_s
     hbm = (batch["t"].nbytes + batch["n_flux"] * 4 + 256 * 8 * 8)
+    traffic = None
+    if FETCH_KIB is not None and WRITE_KIB is not None:
+        traffic = (FETCH_KIB * FETCH_SCALE + WRITE_KIB * WRITE_SCALE) * 1024.0
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_ALU, "traffic": traffic,
+            "kernel": "k_lc_batch<fp32, MA> (+ two small setup kernels)", "kernel_ms": kernel_s * 1e3,
+            "algorithmic_flops_per_launch": flops, **u,
+            "hbm_bytes_algorithmic": hbm, "hbm_frac": hbm / kernel_s / HBM_PEAK}
+    if VALU_INSTS_PER_LAUNCH is not None:
+        roof["valu_issue_frac"] = VALU_INSTS_PER_LAUNCH / kernel_s / PEAK_VALU_ISSUE
     line = {
         "metric": "model points/sec (incl. supersamples) at max|dF|<=1e-5 vs FP64, surrogate vs plain",
         "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -224,12 +254,7 @@ def main():
         "config": {"workload": batch["name"], "light_curves": 256, "exposures": int(batch["t_count"][0]),
                    "subsamples": 10, "bands": 1, "model": "quadratic Mandel-Agol", "precision": "fp32 path",
                    "points_per_step": points, "tile_exposures": tile_e, "workgroups": wg},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_ALU, "traffic": None,
-                     "kernel": "k_lc_batch<fp32, MA> (+ prep)", "kernel_ms": kernel_s * 1e3,
-                     "algorithmic_flops_per_launch": flops, "orbit_points": n_orbit,
-                     "in_transit_points": n_in, "hbm_bytes_algorithmic": hbm,
-                     "hbm_frac": hbm / kernel_s / HBM_PEAK},
+        "roofline": roof,
     }
     from oracle import oracle as O
     line["max_abs_dF_sampled"] = sampled_error(pthip, O, batch, flux)

@@ -58,6 +58,13 @@ template <> struct Num<float> {
   // [0, 1], atan t by an odd polynomial of degree 17 whose coefficients were
   // fitted to atan on [0, 1] by Lawson's iteratively reweighted least squares
   // (maximum error 5.8e-9), then the octant is restored.
+  PT_HD static float rsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / ::sqrtf(x);
+#endif
+  }
   PT_HD static float atan2(float y, float x) {
     const float ax = fabsf(x);
     const float lo = fminf(ax, y), hi = fmaxf(ax, y);
@@ -92,6 +99,7 @@ template <> struct Num<float> {
 template <> struct Num<double> {
   PT_HD static double sqrt(double x) { return ::sqrt(x); }
   PT_HD static double rcp(double x) { return 1.0 / x; }
+  PT_HD static double rsqrt(double x) { return 1.0 / ::sqrt(x); }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -132,6 +140,15 @@ struct NumFast {
     const double s = x * y;
     const double r = fma(-s, s, x);          // x - s^2
     return fma(0.5 * y, r, s);
+  }
+  PT_HD static double rsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+#else
+    const double y = (double)(1.0f / ::sqrtf((float)x));
+#endif
+    const double r = fma(-x * y, y, 1.0);    // 1 - x y^2
+    return fma(0.5 * y, r, y);
   }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) { Num<double>::sincos(x, s, c); }
@@ -180,20 +197,21 @@ PT_HD void sin_vers(T x, T* s, T* v) {
 // keeps the integral's form, moves the modulus pair along the arithmetic-
 // geometric mean and updates (p, a, b); the result is read off once the mean
 // has converged.  Two integrals sharing kc are evaluated in one pass: the
-// mean is common, only (p, a, b) differ.  The caller passes sqrt(p), which it
-// can often form without cancellation.
+// mean is common, only (p, a, b) differ, and one reciprocal of p1 p2 serves
+// both integrals in each step.  The caller passes sqrt(p) and b / sqrt(p),
+// which it can often form without cancellation or division.
 // ---------------------------------------------------------------------------
 template <class T> struct CelPair { T r1, r2; };
 
 template <class T, int FIXED_ITERS, class Op = Num<T>>
-PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T b1, T sp2, T a2, T b2) {
+PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
   T mu = T(1), kk = kc, prod = kc;
   T p1 = sp1, p2 = sp2;
-  b1 = b1 * Op::rcp(sp1);
-  b2 = b2 * Op::rcp(sp2);
+  T b1 = bt1, b2 = bt2;
   // One Gauss step; returns false once the mean has converged.
   auto step = [&](bool last) {
-    const T r1 = Op::rcp(p1), r2 = Op::rcp(p2);
+    const T rp = Op::rcp(p1 * p2);
+    const T r1 = p2 * rp, r2 = p1 * rp;
     const T g1 = prod * r1, g2 = prod * r2;
     const T f1 = a1, f2 = a2;
     a1 = a1 + b1 * r1;
@@ -218,9 +236,11 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T b1, T sp2, T a2, T b2) {
       if (!step(false)) break;
   }
   const T hp = T(0.5 * kPi);
+  const T d1 = mu * (mu + p1), d2 = mu * (mu + p2);
+  const T rd = hp * Op::rcp(d1 * d2);
   CelPair<T> r;
-  r.r1 = hp * (b1 + a1 * mu) * Op::rcp(mu * (mu + p1));
-  r.r2 = hp * (b2 + a2 * mu) * Op::rcp(mu * (mu + p2));
+  r.r1 = (b1 + a1 * mu) * d2 * rd;
+  r.r2 = (b2 + a2 * mu) * d1 * rd;
   return r;
 }
 
@@ -454,31 +474,35 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 template <class T, int ITERS, class Op = Num<T>>
 PT_HD T ma_elliptic(T z, T k, bool limb) {
   const T zmk = z - k, zpk = z + k;
-  const T a = zmk * zmk, b = zpk * zpk;
-  const T q = (k - z) * (k + z);
   const T z2 = z * z, k2 = k * k;
   const T azmk = fabs(zmk);
-  T kc, ck, ce, sp, pref;
+  const T sgn = zmk > T(0) ? T(1) : T(-1);
+  const T rz = Op::rcp(azmk);                              // 1 / |z-k| = sqrt(1/a)
+  T kc, ck, ce, sp, pref, bt2;
   if (limb) {
+    const T a = zmk * zmk, b = zpk * zpk;
+    const T q = (k - z) * (k + z);
     const T bm1 = (zpk - T(1)) * (zpk + T(1));              // b - 1
-    kc = Op::sqrt(bm1 * Op::rcp(T(4) * z * k));
+    kc = bm1 > T(0) ? bm1 * Op::rsqrt(bm1 * (T(4) * z * k)) : T(0);   // sqrt((b-1)/(4zk))
     ck = (T(1) - b) * (T(2) * b + a - T(3)) - T(3) * q * (b - T(2));
     ce = T(4) * z * k * (z2 + T(7) * k2 - T(4));
-    sp = Op::rcp(azmk);                                  // sqrt(1/a)
-    pref = T(1.0 / (9.0 * kPi)) * Op::rcp(Op::sqrt(k * z));
+    sp = rz;                                              // sqrt(p) = sqrt(1/a)
+    pref = T(1.0 / (9.0 * kPi)) * Op::rsqrt(k * z);
+    bt2 = T(3) * zpk * sgn;                               // C_P / sqrt(p)
   } else {
+    const T q = (k - z) * (k + z);
     const T oma = (T(1) - zmk) * (T(1) + zmk);              // 1 - a
     const T omb = (T(1) - zpk) * (T(1) + zpk);              // 1 - b
-    kc = Op::sqrt(omb * Op::rcp(oma));
+    kc = omb > T(0) ? omb * Op::rsqrt(omb * oma) : T(0);    // sqrt((1-b)/(1-a))
     ck = T(1) - T(5) * z2 + k2 + q * q;
     ce = oma * (z2 + T(7) * k2 - T(4));
-    sp = zpk * Op::rcp(azmk);                            // sqrt(b/a)
-    pref = T(2.0 / (9.0 * kPi)) * Op::rcp(Op::sqrt(oma));
+    sp = zpk * rz;                                        // sqrt(p) = sqrt(b/a)
+    pref = T(2.0 / (9.0 * kPi)) * Op::rsqrt(oma);
+    bt2 = T(3) * sgn;                                     // C_P / sqrt(p)
   }
-  // C_P = -3 q / a; with b_Pi = C_P / sqrt(p) the ratio is exact:
-  // limb: -3q/a * |z-k| = 3 (z+k) sign(z-k);  inside: the same times 1/(z+k)
-  const T cp = T(-3) * q * Op::rcp(a);
-  const CelPair<T> r = cel2<T, ITERS, Op>(kc, T(1), ck + ce, ck + ce * kc * kc, sp, cp, cp);
+  // C_P = -3 q / a = 3 (z+k) / (z-k) = 3 sign(z-k) (z+k) / |z-k|
+  const T cp = T(3) * sgn * zpk * rz;
+  const CelPair<T> r = cel2<T, ITERS, Op>(kc, T(1), ck + ce, ck + ce * kc * kc, sp, cp, bt2);
   return pref * (r.r1 + r.r2);
 }
 
