@@ -30,8 +30,8 @@ sys.path.insert(0, ROOT)
 # unit of work (bench.py --mode units; summary and command in
 # profiles/unit_probes_flops.txt):
 F_ORBIT_ECC = 86.0        # orbit of one in-transit point, e > 0: Kepler, z (float part)
-F_MA_INSIDE = 277.7       # Mandel-Agol functions + limb darkening, z < 1 - k
-F_MA_LIMB = 377.3         # the same, 1 - k < z < 1 + k
+F_MA_INSIDE = 249.6       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 351.4         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8).
 F_POINT, F_EXPOSURE = 5.0, 8.0
@@ -42,17 +42,18 @@ HBM_PEAK = 8.0e12
 # (profiles/k_lc_batch_fp32_ma_long_cadence_counters.txt): wave64 VALU
 # instructions per launch, and HBM bytes per launch from FETCH_SIZE and
 # WRITE_SIZE (KiB) scaled by what the counters read for an elementwise kernel
-# that reads and writes 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
-VALU_INSTS_PER_LAUNCH = None
-FETCH_KIB, WRITE_KIB = None, None
-FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+# that reads and writes 1 GiB (FETCH_SIZE reads 524316 KiB for 1 GiB read,
+# WRITE_SIZE 1048580 KiB for 1 GiB written).
+VALU_INSTS_PER_LAUNCH = 1.18427e9
+FETCH_KIB, WRITE_KIB = 19553.2, 203480.3
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524316, 1.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-side", action="store_true", help="skip the side paths")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -263,8 +264,8 @@ def main():
     if not args.no_side:
         paths = {}
         flux64 = torch.empty(batch["n_flux"], dtype=torch.float64, device="cuda")
-        w64, _ = timed(lambda: pthip.lc_batch(db, "ma", prec="fp64", out=flux64), max(2, args.steps // 5), 1)
         s64 = max(2, args.steps // 5)
+        w64, _ = timed(lambda: pthip.lc_batch(db, "ma", prec="fp64", out=flux64), s64, 5)
         paths["ma_fp64_same_workload"] = {"points_per_s": points * s64 / w64, "ms_per_step": w64 / s64 * 1e3,
                                           "max_abs_dF_sampled": sampled_error(pthip, O, batch, flux64, 1000)}
         paths["fp32_over_fp64_speedup"] = paths["ma_fp64_same_workload"]["ms_per_step"] / ms
@@ -274,12 +275,12 @@ def main():
         d3g = pthip.DeviceBatch(b3, u=ug)
         p3 = W.n_points(b3)
         f3 = torch.empty(b3["n_flux"], dtype=torch.float32, device="cuda")
-        w3, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="fp32", out=f3), 10, 2)
-        paths["ma_fp32_spectrophotometric"] = {"workload": b3["name"], "points_per_s": p3 * 10 / w3,
-                                               "ms_per_step": w3 / 10 * 1e3}
-        w3g, _ = timed(lambda: pthip.lc_batch(d3g, "gimenez", npol=50, prec="fp32", out=f3), 5, 1)
+        w3, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="fp32", out=f3), 20, 10)
+        paths["ma_fp32_spectrophotometric"] = {"workload": b3["name"], "points_per_s": p3 * 20 / w3,
+                                               "ms_per_step": w3 / 20 * 1e3}
+        w3g, _ = timed(lambda: pthip.lc_batch(d3g, "gimenez", npol=50, prec="fp32", out=f3), 10, 3)
         paths["gimenez50_fp32_spectrophotometric"] = {
-            "workload": b3["name"], "points_per_s": p3 * 5 / w3g, "ms_per_step": w3g / 5 * 1e3,
+            "workload": b3["name"], "points_per_s": p3 * 10 / w3g, "ms_per_step": w3g / 10 * 1e3,
             "max_abs_dF_sampled": sampled_error(pthip, O, b3, f3, 200, model=1, u=ug)}
         ckpt = os.path.join(ROOT, "paper_1504_07433_amd", "data", "surrogate.npz")
         if os.path.exists(ckpt):
@@ -288,13 +289,13 @@ def main():
             sur.load(ckpt)
             frac = sur.install()
             f3s = torch.empty(b3["n_flux"], dtype=torch.float32, device="cuda")
-            w3s, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="surrogate", out=f3s), 5, 1)
+            w3s, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="surrogate", out=f3s), 10, 3)
             paths["ma_surrogate_spectrophotometric"] = {
-                "workload": b3["name"], "points_per_s": p3 * 5 / w3s, "ms_per_step": w3s / 5 * 1e3,
+                "workload": b3["name"], "points_per_s": p3 * 10 / w3s, "ms_per_step": w3s / 10 * 1e3,
                 "trusted_cell_fraction": frac,
                 "max_abs_dF_sampled": sampled_error(pthip, O, b3, f3s, 300, seed=4)}
-            paths["surrogate_over_plain_fp32"] = (w3 / 10) / (w3s / 5)
-            paths["surrogate_over_plain_fp64_long_cadence_rate"] = (p3 * 5 / w3s) / paths["ma_fp64_same_workload"]["points_per_s"]
+            paths["surrogate_over_plain_fp32"] = (w3 / 20) / (w3s / 10)
+            paths["surrogate_over_plain_fp64_long_cadence_rate"] = (p3 * 10 / w3s) / paths["ma_fp64_same_workload"]["points_per_s"]
         line["paths"] = paths
 
     if not args.no_cpu:
