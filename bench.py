@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--mode", choices=("full", "kernel", "units"), default="full",
                     help="kernel: only the timed batch launches (for profilers); units: divergence-free "
                          "launches of each unit of work, for counting operations per unit")
+    ap.add_argument("--kernel-model", choices=("ma", "ma_interp"), default="ma",
+                    help="model timed by --mode kernel (ma_interp: tables over the batch's k range, 256 x 2048)")
     return ap.parse_args()
 
 
@@ -216,6 +218,13 @@ def main():
     db = pthip.DeviceBatch(batch)
     points = W.n_points(batch)
     flux = torch.empty(batch["n_flux"], dtype=torch.float32, device="cuda")
+    if args.mode == "kernel" and args.kernel_model == "ma_interp":
+        pthip.ma_table_set(float(batch["k"].min()), float(batch["k"].max()), 256, 2048)
+        step = lambda: pthip.lc_batch(db, "ma_interp", prec="fp32", out=flux)
+        wall, _ = timed(step, args.steps, args.warmup)
+        print(json.dumps({"mode": "kernel", "model": "ma_interp", "ms_per_step": wall / args.steps * 1e3,
+                          "points_per_s": points * args.steps / wall}), flush=True)
+        return
     if args.autotune:
         rep = pthip.autotune(db, "ma", prec="fp32", out=flux)
         print(json.dumps({"autotune": rep}), file=sys.stderr, flush=True)
@@ -269,6 +278,28 @@ def main():
         paths["ma_fp64_same_workload"] = {"points_per_s": points * s64 / w64, "ms_per_step": w64 / s64 * 1e3,
                                           "max_abs_dF_sampled": sampled_error(pthip, O, batch, flux64, 1000)}
         paths["fp32_over_fp64_speedup"] = paths["ma_fp64_same_workload"]["ms_per_step"] / ms
+        # the paper's tabulated model (Sect. 2.2.3) on the same workload: tables over
+        # the batch's k range, error measured against the exact oracle
+        k_lo, k_hi = float(batch["k"].min()), float(batch["k"].max())
+        pthip.ma_table_set(k_lo, k_hi, 256, 2048)
+        wi, _ = timed(lambda: pthip.lc_batch(db, "ma_interp", prec="fp32", out=flux), args.steps, args.warmup)
+        paths["ma_interp_fp32_same_workload"] = {
+            "table": {"k_lo": k_lo, "k_hi": k_hi, "nk": 256, "nz": 2048},
+            "points_per_s": points * args.steps / wi, "ms_per_step": wi / args.steps * 1e3,
+            "max_abs_dF_sampled_vs_exact": sampled_error(pthip, O, batch, flux)}
+        paths["interp_over_plain_fp64"] = paths["ma_interp_fp32_same_workload"]["points_per_s"] / \
+            paths["ma_fp64_same_workload"]["points_per_s"]
+        paths["interp_over_plain_fp32"] = ms / paths["ma_interp_fp32_same_workload"]["ms_per_step"]
+        b4 = W.config4()
+        d4 = pthip.DeviceBatch(b4)
+        p4 = W.n_points(b4)
+        f4 = torch.empty(b4["n_flux"], dtype=torch.float32, device="cuda")
+        w4, _ = timed(lambda: pthip.lc_batch(d4, "ma", prec="fp32", out=f4), 10, 3)
+        te4, wg4 = pthip.launch_shape(d4, "ma", prec="fp32")
+        paths["ma_fp32_uneven"] = {"workload": b4["name"], "points": p4, "points_per_s": p4 * 10 / w4,
+                                   "ms_per_step": w4 / 10 * 1e3, "tile_exposures": te4, "workgroups": wg4,
+                                   "max_abs_dF_sampled": sampled_error(pthip, O, b4, f4, 1000, seed=7)}
+        del d4, f4
         b3 = W.config3()
         d3 = pthip.DeviceBatch(b3)
         ug = np.stack([b3["u"][:, 0] + 2 * b3["u"][:, 1], -b3["u"][:, 1]], 1)

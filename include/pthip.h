@@ -118,7 +118,10 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
  * double path on a uniform grid of nk radius ratios in [k_lo, k_hi] and nz
  * distances in [0, 1 + k_hi]; evaluation is bilinear in (k, z).  Radius
  * ratios outside [k_lo, k_hi] use the exact float path.  The table is
- * library-owned (one per device) and ready when the call returns.
+ * library-owned (one per device) and ready when the call returns.  Each
+ * pt_lc_batch call with PT_MODEL_MA_INTERP also keeps 2 nz floats per
+ * passband (the band's weighted sum at the z nodes, as pairs of neighbours)
+ * in its cached batch plan.
  * Errors: PT_ERR_ARG unless 0 < k_lo < k_hi, nk >= 2, nz >= 2,
  * nk * nz <= 2^24. */
 pt_status pt_ma_table_set(double k_lo, double k_hi, int32_t nk, int32_t nz, void* stream);

@@ -44,6 +44,7 @@ enum : int { kModelMA = 0, kModelGimenez = 1, kModelMAInterp = 2, kModelMAKhat =
 struct MaTable {
   const float4* tab;    // [nk][nz] {lambda_e, lambda_d + 2/3 Theta, eta_d, 0}
   float k_lo, k_hi, z_hi;
+  float inv_dk, inv_dz; // (nk-1)/(k_hi-k_lo), (nz-1)/z_hi
   int32_t nk, nz;
 };
 
@@ -95,6 +96,7 @@ struct BatchArgs {
   const int64_t* n_obs; // [n_lc] points per light curve (bands x exposures)
   double* loglike;      // [n_lc]
   MaTable matab;        // kModelMAInterp
+  float2* ltab;         // [n_band][matab.nz] (L_j, L_j+1): loss at the z nodes for the band's k
   double* khat;         // [n_lc] mean radius ratio (kModelMAKhat), written by prep
   float* ztab;          // [n_band][zin + zlimb] loss at the z nodes (kModelGimenezZInterp)
   int32_t zin, zlimb;

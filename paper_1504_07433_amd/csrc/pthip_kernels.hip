@@ -381,22 +381,38 @@ __device__ __forceinline__ float ma_loss_surrogate(float z, const BandConst* __r
 
 // Bilinear interpolation of the three functions (Sect. 2.2.3); k outside the
 // table's range falls back to the float path.
-__device__ __forceinline__ float ma_loss_interp(float z, const BandConst* __restrict__ bc, const MaTable& t) {
-  if (z < 0.0f || z >= bc->onepk) return 0.0f;
-  const float k = bc->kf;
-  if (!(k >= t.k_lo && k <= t.k_hi)) return ma_loss<float>(z, bc);
-  const float fk = (k - t.k_lo) / (t.k_hi - t.k_lo) * (t.nk - 1);
-  const float fz = z / t.z_hi * (t.nz - 1);
-  const int ik = min(t.nk - 2, max(0, (int)fk));
-  const int iz = min(t.nz - 2, max(0, (int)fz));
-  const float wk = fk - ik, wz = fz - iz;
-  const float4 a = t.tab[ik * t.nz + iz], b = t.tab[ik * t.nz + iz + 1];
-  const float4 c = t.tab[(ik + 1) * t.nz + iz], d = t.tab[(ik + 1) * t.nz + iz + 1];
-  const float w00 = (1 - wk) * (1 - wz), w01 = (1 - wk) * wz, w10 = wk * (1 - wz), w11 = wk * wz;
-  const float le = w00 * a.x + w01 * b.x + w10 * c.x + w11 * d.x;
-  const float ld = w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y;
-  const float ed = w00 * a.z + w01 * b.z + w10 * c.z + w11 * d.z;
-  return bc->wf[0] * le + bc->wf[1] * ld + bc->wf[2] * ed;
+// Interpolated model (Sect. 2.2.3): bilinear interpolation in (k, z) of the
+// tabulated functions, then the band's limb-darkening weights.  Bilinear
+// interpolation is linear in k, then linear in z, so for a band of fixed k the
+// weighted sum can be formed once per call at the z nodes (k_ma_band_ltab)
+// and each point interpolates one row linearly in z.  Bands whose k lies
+// outside the table take the exact functions.
+__device__ __forceinline__ float ma_band_node(const MaTable& t, const BandConst& bc, int ik, float wk, int j) {
+  const float4 p = t.tab[(int64_t)ik * t.nz + j], q = t.tab[(int64_t)(ik + 1) * t.nz + j];
+  const float le = p.x + wk * (q.x - p.x), ld = p.y + wk * (q.y - p.y), ed = p.z + wk * (q.z - p.z);
+  return bc.wf[0] * le + bc.wf[1] * ld + bc.wf[2] * ed;
+}
+
+// Row j of a band holds the pair (L_j, L_{j+1}), so that a point reads both
+// ends of its interval with one 8-byte load.
+__global__ __launch_bounds__(256) void k_ma_band_ltab(BatchArgs a) {
+  const MaTable& t = a.matab;
+  const int64_t total = (int64_t)a.n_band * t.nz, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t bnd = e / t.nz;
+    const int j = (int)(e % t.nz);
+    const BandConst& bc = a.bc[bnd];
+    const float k = bc.kf;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (k >= t.k_lo && k <= t.k_hi) {
+      const float fk = (k - t.k_lo) * t.inv_dk;
+      const int ik = min(t.nk - 2, max(0, (int)fk));
+      const float wk = fk - ik;
+      v.x = ma_band_node(t, bc, ik, wk, j);
+      v.y = j + 1 < t.nz ? ma_band_node(t, bc, ik, wk, j + 1) : v.x;
+    }
+    a.ltab[e] = v;
+  }
 }
 
 // Table of the three functions from the exact double path.
@@ -460,7 +476,31 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   T acc = T(0);
   if constexpr (MODEL == kModelMAInterp) {
-    for (int s = 0; s < ns; ++s) acc += ma_loss_interp(zb[s * kWave + lane], bc, a.matab);
+    const MaTable& t = a.matab;
+    if (bc->kf >= t.k_lo && bc->kf <= t.k_hi) {
+      // all of the chunk's table reads are issued before the first is used
+      const float2* __restrict__ L = a.ltab + (int64_t)bnd * t.nz;
+      float2 v[kZChunk];
+      float wz[kZChunk];
+#pragma unroll
+      for (int s = 0; s < kZChunk; ++s) {
+        v[s] = make_float2(0.0f, 0.0f);
+        wz[s] = 0.0f;
+        if (s < ns) {
+          const float z = zb[s * kWave + lane];
+          if (z >= 0.0f && z < bc->onepk) {
+            const float fz = z * t.inv_dz;
+            const int iz = min(t.nz - 2, (int)fz);
+            wz[s] = fz - iz;
+            v[s] = L[iz];
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < kZChunk; ++s) acc += v[s].x + wz[s] * (v[s].y - v[s].x);
+    } else {
+      for (int s = 0; s < ns; ++s) acc += ma_loss<float>(zb[s * kWave + lane], bc);
+    }
   } else if constexpr (MODEL == kModelGimenezZInterp) {
     // k >= 1 has no inner grid: direct series
     const float* zt = a.ztab + (int64_t)bnd * (a.zin + a.zlimb);
@@ -715,6 +755,11 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
     err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gaprime, a.gtab, prec, s);
+    if (err != hipSuccess) return err;
+  }
+  if (model == kModelMAInterp) {
+    hipLaunchKernelGGL(k_ma_band_ltab, dim3(grid_for((int64_t)a.n_band * a.matab.nz, 256)), dim3(256), 0, s, a);
+    err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
   if (model == kModelGimenezZInterp) {

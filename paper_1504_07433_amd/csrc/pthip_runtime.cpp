@@ -182,7 +182,7 @@ struct Plan {
   int32_t n_lc = 0, n_band = 0, nldc = 0, npol = 0, model = 0, prec = 0;
   std::vector<int64_t> t_count;
   std::vector<int32_t> nss, band_off;
-  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, queue, khat, ztab;
+  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, queue, khat, ztab, ltab;
   std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
   LaunchShape shape;
   bool tuned = false;
@@ -455,6 +455,8 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     if (p->dev < 0 || p->dev >= 16 || !g_matab[p->dev].ready)
       return fail(PT_ERR_UNSUPPORTED, "no interpolation table on this device (pt_ma_table_set)");
     a->matab = g_matab[p->dev].t;
+    PT_HIP(p->ltab.ensure(std::max<size_t>(1, (size_t)p->n_band) * a->matab.nz * sizeof(float2)));
+    a->ltab = (float2*)p->ltab.p;
   }
   if (p->model == PT_MODEL_GIMENEZ_ZINTERP) {
     PT_HIP(p->ztab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (g_zin + g_zlimb) * sizeof(float)));
@@ -649,6 +651,8 @@ pt_status pt_ma_table_set(double k_lo, double k_hi, int32_t nk, int32_t nz, void
   st.t.k_lo = (float)k_lo;
   st.t.k_hi = (float)k_hi;
   st.t.z_hi = (float)(1.0 + k_hi);
+  st.t.inv_dk = (float)((nk - 1) / (k_hi - k_lo));
+  st.t.inv_dz = (float)((nz - 1) / (1.0 + k_hi));
   st.t.nk = nk;
   st.t.nz = nz;
   st.ready = true;
