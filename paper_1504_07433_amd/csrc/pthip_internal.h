@@ -48,6 +48,13 @@ struct MaTable {
   int32_t nk, nz;
 };
 
+// The tile queue is split into kQueues sub-queues (tile q + i kQueues is the
+// i-th tile of sub-queue q), each with its own counter on its own 128-byte
+// line: one counter serialises its atomics at the memory side, and the pops
+// of all waves of the GPU otherwise meet on it.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;   // unsigned ints between counters
+
 // Subsamples whose z values a wave keeps in LDS at once.
 constexpr int kZChunk = 16;
 constexpr int kWave = 64;
@@ -77,7 +84,7 @@ struct BatchArgs {
   void* gtab;           // Gimenez per-band tables [n_band][nldc+1][npol] (float or double)
   const void* grec;     // shared recurrence coefficients [(nldc+1)][npol][3]
   const double* gaprime;  // A'_{n,j} [(nldc+1)][npol]
-  unsigned int* queue;  // [0] next tile (reset by the prep kernel)
+  unsigned int* queue;  // kQueues counters, kQueueStride apart (reset by the prep kernel)
   void* flux;
   int64_t n_tiles;
   int32_t n_lc;

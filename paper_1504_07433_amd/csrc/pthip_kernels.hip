@@ -233,7 +233,7 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
 }
 
 __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.queue[0] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kQueues) a.queue[threadIdx.x * kQueueStride] = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_band; i += stride)
     a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
@@ -308,7 +308,8 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
 
 // ---------------------------------------------------------------------------
 // Persistent fused batch kernel.  Each wavefront takes tiles (a light curve's
-// run of exposures) from a global queue, lanes = consecutive exposures:
+// run of exposures) from a global queue (kQueues sub-queues), lanes =
+// consecutive exposures:
 //  1. for a chunk of up to 16 subsamples it solves the orbit once per
 //     (exposure, subsample) and keeps z in its own slice of LDS;
 //  2. for every passband it evaluates the model at those z, accumulates the
@@ -550,11 +551,22 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
   const T* __restrict__ obs = reinterpret_cast<const T*>(a.obs);
   const int64_t tab_stride = (int64_t)(a.nldc + 1) * gim_row(a.npol);
 
+  // Start on the sub-queue of this workgroup's slot (workgroups are handed to
+  // the XCDs in turn), move to the next one when it runs dry, stop when all
+  // have: every wave ends after at most its tiles + kQueues pops.
+  int q = (int)(blockIdx.x % kQueues);
+  int dry = 0;
   for (;;) {
-    unsigned int tid = 0;
-    if (lane == 0) tid = atomicAdd(a.queue, 1u);
-    tid = __builtin_amdgcn_readfirstlane(tid);
-    if (tid >= (uint64_t)a.n_tiles) break;
+    unsigned int pos = 0;
+    if (lane == 0) pos = atomicAdd(a.queue + q * kQueueStride, 1u);
+    pos = __builtin_amdgcn_readfirstlane(pos);
+    const uint64_t tile = (uint64_t)pos * kQueues + q;
+    if (tile >= (uint64_t)a.n_tiles) {
+      if (++dry == kQueues) break;
+      q = q + 1 == kQueues ? 0 : q + 1;
+      continue;
+    }
+    const unsigned int tid = (unsigned int)tile;
     const TileDesc td = load_uniform(a.tiles + tid);
     const int lc = td.lc;
     constexpr bool F32 = sizeof(T) == 4;

@@ -337,7 +337,7 @@ static int kernel_prec(const Plan* p) {
 static int default_tile(const pt_batch* b) {
   // About 24 tiles per resident wave (16 per CU) keeps the tail of the queue
   // short; tiles below 512 exposures only when the batch is small, since
-  // every tile costs one atomic on the shared queue counter.
+  // every tile costs one atomic on a queue counter.
   int64_t expo = 0;
   for (int32_t i = 0; i < b->n_lc; ++i) expo += b->t_count[i] * (b->band_off[i + 1] > b->band_off[i]);
   const int cu = std::max(1, cu_count());
@@ -389,8 +389,8 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   PT_HIP(p->oc.ensure(std::max<size_t>(1, n) * sizeof(OrbitConst)));
   PT_HIP(p->ocf.ensure(std::max<size_t>(1, n) * sizeof(OrbitF)));
   PT_HIP(p->bc.ensure(std::max<size_t>(1, (size_t)p->n_band) * sizeof(BandConst)));
-  PT_HIP(p->queue.ensure(64));
-  PT_HIP(hipMemset(p->queue.p, 0, 64));
+  PT_HIP(p->queue.ensure(kQueues * kQueueStride * sizeof(unsigned int)));
+  PT_HIP(hipMemset(p->queue.p, 0, kQueues * kQueueStride * sizeof(unsigned int)));
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
     const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
