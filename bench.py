@@ -309,6 +309,12 @@ def main():
         w3, _ = timed(lambda: pthip.lc_batch(d3, "ma", prec="fp32", out=f3), 20, 10)
         paths["ma_fp32_spectrophotometric"] = {"workload": b3["name"], "points_per_s": p3 * 20 / w3,
                                                "ms_per_step": w3 / 20 * 1e3}
+        pthip.ma_table_set(0.09, 0.11, 16, 2048)
+        w3i, _ = timed(lambda: pthip.lc_batch(d3, "ma_interp", prec="fp32", out=f3), 20, 10)
+        paths["ma_interp_fp32_spectrophotometric"] = {
+            "workload": b3["name"], "table": {"k_lo": 0.09, "k_hi": 0.11, "nk": 16, "nz": 2048},
+            "points_per_s": p3 * 20 / w3i, "ms_per_step": w3i / 20 * 1e3,
+            "max_abs_dF_sampled_vs_exact": sampled_error(pthip, O, b3, f3, 500, seed=3)}
         w3g, _ = timed(lambda: pthip.lc_batch(d3g, "gimenez", npol=50, prec="fp32", out=f3), 10, 3)
         paths["gimenez50_fp32_spectrophotometric"] = {
             "workload": b3["name"], "points_per_s": p3 * 10 / w3g, "ms_per_step": w3g / 10 * 1e3,

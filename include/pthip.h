@@ -121,7 +121,8 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
  * library-owned (one per device) and ready when the call returns.  Each
  * pt_lc_batch call with PT_MODEL_MA_INTERP also keeps 2 nz floats per
  * passband (the band's weighted sum at the z nodes, as pairs of neighbours)
- * in its cached batch plan.
+ * in its cached batch plan when these take at most 64 MB; larger batches
+ * interpolate the shared table directly (same values up to rounding).
  * Errors: PT_ERR_ARG unless 0 < k_lo < k_hi, nk >= 2, nz >= 2,
  * nk * nz <= 2^24. */
 pt_status pt_ma_table_set(double k_lo, double k_hi, int32_t nk, int32_t nz, void* stream);

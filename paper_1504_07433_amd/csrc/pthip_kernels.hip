@@ -386,7 +386,8 @@ __device__ __forceinline__ float ma_loss_surrogate(float z, const BandConst* __r
 // tabulated functions, then the band's limb-darkening weights.  Bilinear
 // interpolation is linear in k, then linear in z, so for a band of fixed k the
 // weighted sum can be formed once per call at the z nodes (k_ma_band_ltab)
-// and each point interpolates one row linearly in z.  Bands whose k lies
+// and each point interpolates one row linearly in z; batches with too many
+// bands for such rows read the shared table directly.  Bands whose k lies
 // outside the table take the exact functions.
 __device__ __forceinline__ float ma_band_node(const MaTable& t, const BandConst& bc, int ik, float wk, int j) {
   const float4 p = t.tab[(int64_t)ik * t.nz + j], q = t.tab[(int64_t)(ik + 1) * t.nz + j];
@@ -478,8 +479,32 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
   T acc = T(0);
   if constexpr (MODEL == kModelMAInterp) {
     const MaTable& t = a.matab;
-    if (bc->kf >= t.k_lo && bc->kf <= t.k_hi) {
-      // all of the chunk's table reads are issued before the first is used
+    if (bc->kf >= t.k_lo && bc->kf <= t.k_hi && !a.ltab) {
+      // bilinear in (k, z) from the shared table (batches with many bands);
+      // the k row pair and weight are the band's, the z cell the point's
+      const float fk = (bc->kf - t.k_lo) * t.inv_dk;
+      const int ik = min(t.nk - 2, max(0, (int)fk));
+      const float wk = fk - ik;
+      const float4* __restrict__ r0 = t.tab + (int64_t)ik * t.nz;
+      const float4* __restrict__ r1 = r0 + t.nz;
+      for (int s = 0; s < ns; ++s) {
+        const float z = zb[s * kWave + lane];
+        if (z >= 0.0f && z < bc->onepk) {
+          const float fz = z * t.inv_dz;
+          const int iz = min(t.nz - 2, (int)fz);
+          const float wz = fz - iz;
+          const float4 p0 = r0[iz], p1 = r0[iz + 1], q0 = r1[iz], q1 = r1[iz + 1];
+          const float4 p = make_float4(p0.x + wz * (p1.x - p0.x), p0.y + wz * (p1.y - p0.y),
+                                       p0.z + wz * (p1.z - p0.z), 0.0f);
+          const float4 q = make_float4(q0.x + wz * (q1.x - q0.x), q0.y + wz * (q1.y - q0.y),
+                                       q0.z + wz * (q1.z - q0.z), 0.0f);
+          acc += bc->wf[0] * (p.x + wk * (q.x - p.x)) + bc->wf[1] * (p.y + wk * (q.y - p.y)) +
+                 bc->wf[2] * (p.z + wk * (q.z - p.z));
+        }
+      }
+    } else if (bc->kf >= t.k_lo && bc->kf <= t.k_hi) {
+      // the band's pre-combined row; all of the chunk's reads are issued
+      // before the first is used
       const float2* __restrict__ L = a.ltab + (int64_t)bnd * t.nz;
       float2 v[kZChunk];
       float wz[kZChunk];
@@ -769,7 +794,7 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
     err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gaprime, a.gtab, prec, s);
     if (err != hipSuccess) return err;
   }
-  if (model == kModelMAInterp) {
+  if (model == kModelMAInterp && a.ltab) {
     hipLaunchKernelGGL(k_ma_band_ltab, dim3(grid_for((int64_t)a.n_band * a.matab.nz, 256)), dim3(256), 0, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;

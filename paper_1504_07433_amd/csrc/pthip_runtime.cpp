@@ -455,8 +455,15 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     if (p->dev < 0 || p->dev >= 16 || !g_matab[p->dev].ready)
       return fail(PT_ERR_UNSUPPORTED, "no interpolation table on this device (pt_ma_table_set)");
     a->matab = g_matab[p->dev].t;
-    PT_HIP(p->ltab.ensure(std::max<size_t>(1, (size_t)p->n_band) * a->matab.nz * sizeof(float2)));
-    a->ltab = (float2*)p->ltab.p;
+    // per-band pre-combined rows while they take at most 64 MB; beyond
+    // that the kernel reads the shared (k, z) table
+    const size_t rows = (size_t)p->n_band * a->matab.nz * sizeof(float2);
+    if (rows <= (size_t(64) << 20)) {
+      PT_HIP(p->ltab.ensure(std::max<size_t>(1, rows)));
+      a->ltab = (float2*)p->ltab.p;
+    } else {
+      a->ltab = nullptr;
+    }
   }
   if (p->model == PT_MODEL_GIMENEZ_ZINTERP) {
     PT_HIP(p->ztab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (g_zin + g_zlimb) * sizeof(float)));

@@ -244,9 +244,6 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
   return r;
 }
 
-// Gauss steps the float path needs: the bulk path keeps kc >= 0.02, where
-// five steps bring the mean to float precision.
-constexpr int kCelItersF32 = 5;
 
 // ---------------------------------------------------------------------------
 // Orbit.  Per-light-curve constants are formed once in double precision; the
@@ -521,25 +518,6 @@ PT_HD void ma_limb_terms(T z, T k, T* le, T* ed) {
   *le = (k2 * kap0 + kap1 - T(0.5) * sD) * T(1.0 / kPi);
   const T eta2 = T(0.5) * k2 * (k2 + T(2) * z2);
   *ed = (kap1 + T(2) * eta2 * kap0 - T(0.25) * (T(1) + T(5) * k2 + z2) * sD) * T(0.5 / kPi);
-}
-
-// Float bulk: valid for k <= 1/2 away from the contact points; callers route
-// the rest to ma_alpha_exact.  z must satisfy 0 <= z < 1 + k.
-template <class T>
-PT_HD MaAlpha<T> ma_alpha_bulk(T z, T k) {
-  MaAlpha<T> r;
-  const bool limb = z > T(1) - k;
-  const T ell = ma_elliptic<T, kCelItersF32>(z, k, limb);
-  if (limb) {
-    ma_limb_terms(z, k, &r.le, &r.ed);
-    r.ld = ell;
-  } else {
-    const T k2 = k * k;
-    r.le = k2;
-    r.ed = T(0.5) * k2 * (k2 + T(2) * z * z);
-    r.ld = ell + (z < k ? T(2.0 / 3.0) : T(0));
-  }
-  return r;
 }
 
 // Fast-path bulk: z and the limb angles in float, the elliptic combination

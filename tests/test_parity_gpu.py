@@ -377,6 +377,20 @@ def test_interpolated_model_matches_oracle(pt, O):
     assert np.abs(got - ref).max() <= TOL32
 
 
+def test_interpolated_model_many_bands_matches_oracle(pt, O):
+    """65536 passbands x 2048 z nodes exceed the size kept for per-band rows,
+    so the kernel interpolates the shared (k, z) table directly."""
+    from paper_1504_07433_amd import workloads as W
+    k_lo, k_hi, nk, nz = 0.09, 0.11, 16, 2048
+    pt.ma_table_set(k_lo, k_hi, nk, nz)
+    tab = O.ma_table(k_lo, k_hi, nk, nz)
+    b = W.config3(n_vec=1024, n_band=64, n_exp=12)
+    b["k"][5] = 0.2                            # outside the table: exact path
+    ref = O.lc_batch_ma_variant(b, "interp", tab, k_lo, k_hi)
+    got = _run(pt, b, "ma_interp", "fp32")
+    assert np.abs(got - ref).max() <= TOL32
+
+
 def test_interpolated_model_meets_flux_gate(pt, O):
     """With 256 x 2048 nodes over the batch's k range the tabulated model
     stays within 1e-5 of the exact flux (measured on the oracle: ~1e-6), also
