@@ -625,13 +625,23 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
     }
     const bool orbit_ok = F32 ? of.valid != 0 : oc.valid != 0;
 
+    // Mean-anomaly offset of the exposure centre, in double, and half the
+    // exposure's span of subsample offsets plus a margin for the float
+    // offsets: an exposure whose whole span lies outside the in-transit
+    // window is out of transit for every subsample and band.
+    const double t0d = F32 ? of.t0 : oc.t0, inv_pd = F32 ? of.inv_p : oc.inv_p;
+    const double half_dm = 2.0 * kPi * inv_pd * texp * (0.5 - 0.5 * inv_nss) + 1e-6;
+    const double cut_lo = F32 ? (double)of.cut_lo : oc.cut_lo, cut_hi = F32 ? (double)of.cut_hi : oc.cut_hi;
+    auto centre_dm = [&](double tm) {
+      const double ph = (tm - t0d) * inv_pd;
+      return 2.0 * kPi * (ph - rint(ph));
+    };
+
     // z for subsamples s0 .. s0+ns-1 of this lane's exposure into LDS
-    auto orbit_chunk = [&](double tm, int s0, int ns) {
+    auto orbit_chunk = [&](double tm, double dmid, int s0, int ns) {
       float dm_hi = 0.0f, dm_lo = 0.0f;
       if constexpr (F32) {
-        // dM at the exposure centre in double, split into two floats
-        const double ph = (tm - of.t0) * of.inv_p;
-        const double dmid = 2.0 * kPi * (ph - rint(ph));
+        // dM at the exposure centre split into two floats
         dm_hi = float(dmid);
         dm_lo = float(dmid - double(dm_hi));
       }
@@ -677,9 +687,16 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
       const int i = eb + lane;
       const bool act_lane = i < e_end;
       const double tm = tl[act_lane ? i : td.e0];
+      const double dmid = centre_dm(tm);
+      const bool lane_out = !act_lane || dmid + half_dm < cut_lo || dmid - half_dm > cut_hi;
+      if (orbit_ok && __all(lane_out)) {
+        // the whole wave is out of transit: the loss is 0 in every band
+        for (int bnd = b0; bnd < b1; ++bnd) finish(T(0), load_uniform(a.bc + bnd), bnd, i, act_lane);
+        continue;
+      }
       if (nss <= kZChunk) {
         // one orbit solve per (exposure, subsample), shared by every band
-        orbit_chunk(tm, 0, nss);
+        orbit_chunk(tm, dmid, 0, nss);
         for (int bnd = b0; bnd < b1; ++bnd) {
           // band constants once per band, by scalar loads
           const BandConst bcv = load_uniform(a.bc + bnd);
@@ -693,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
           T acc = T(0);
           for (int s0 = 0; s0 < nss; s0 += kZChunk) {
             const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
-            orbit_chunk(tm, s0, ns);
+            orbit_chunk(tm, dmid, s0, ns);
             acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride, grec, act);
           }
           finish(acc, bcv, bnd, i, act_lane);
