@@ -42,11 +42,11 @@ HBM_PEAK = 8.0e12
 # (profiles/k_lc_batch_fp32_ma_long_cadence_counters.txt): wave64 VALU
 # instructions per launch, and HBM bytes per launch from FETCH_SIZE and
 # WRITE_SIZE (KiB) scaled by what the counters read for an elementwise kernel
-# that reads and writes 1 GiB (FETCH_SIZE reads 524316 KiB for 1 GiB read,
+# that reads and writes 1 GiB (FETCH_SIZE reads 524315 KiB for 1 GiB read,
 # WRITE_SIZE 1048580 KiB for 1 GiB written).
-VALU_INSTS_PER_LAUNCH = 1.18427e9
-FETCH_KIB, WRITE_KIB = 19553.2, 203480.3
-FETCH_SCALE, WRITE_SCALE = 1048576 / 524316, 1.0
+VALU_INSTS_PER_LAUNCH = 1.12244e9
+FETCH_KIB, WRITE_KIB = 10533.6, 204887.0
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524315, 1.0
 
 
 def parse():
