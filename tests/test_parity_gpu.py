@@ -204,6 +204,12 @@ def test_batch_edge_cases(pt, O):
     for prec, tol in (("fp32", TOL32), ("fp64", TOL64)):
         g = _run(pt, b, "ma", prec)
         assert np.abs(g - ref).max() <= tol, prec
+    # the same ragged batch through the Gimenez kernels
+    ug = _gim_u(b)
+    refg = O.lc_batch(b, model=1, npol=20, u=ug)
+    for prec, tol in (("fp32", TOL32), ("fp64", TOL64)):
+        g = _run(pt, b, "gimenez", prec, npol=20, u=ug)
+        assert np.abs(g - refg).max() <= tol, ("gimenez", prec)
 
 
 def _contact_batch(O, seed, e_max, nss, t_exp):
