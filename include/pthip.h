@@ -20,7 +20,8 @@
  *  - Kernels never trap.  Non-physical values that cannot be checked on the
  *    host (device-resident parameters: e >= 1, aR <= 0, P <= 0, b < 0 or an
  *    inclination with cos i > 1) give NaN flux for the light curves they
- *    belong to; NaN inputs give NaN outputs.
+ *    belong to, and a radius ratio that is not positive and finite gives
+ *    NaN flux for its passband; NaN inputs give NaN outputs.
  *  - z < 0 marks the planet behind the star; its flux is 1.
  *  - Calls on different streams may run concurrently; the library's own
  *    caches are guarded by a mutex.

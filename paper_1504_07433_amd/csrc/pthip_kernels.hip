@@ -671,7 +671,8 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
     };
     auto finish = [&](T acc, const BandConst& bcv, int bnd, int i, bool act_lane) {
       if constexpr (MODEL == kModelMAKhat) acc *= T(bcv.kf * bcv.kf * inv_khat2);
-      const T f = T(1) - acc * T(inv_nss);
+      // a band whose radius ratio is not positive and finite gives NaN throughout
+      const T f = bcv.valid ? T(1) - acc * T(inv_nss) : T(NAN);
       const int64_t idx = fo + (int64_t)(bnd - b0) * cnt + i;
       if (LOGL) {
         if (act_lane) {

@@ -269,10 +269,15 @@ def test_batch_nonphysical_parameters_give_nan(pt):
     b = W.config2(n_vec=4, n_windows=1)
     b["e"][1] = 1.2
     b["aR"][2] = -3.0
+    b["k"][3] = np.nan                         # an invalid band: NaN in every exposure
+    for prec in ("fp32", "fp64"):
+        g = _run(pt, b, "ma", prec)
+        blk = lambda i: g[b["flux_off"][i]:b["flux_off"][i] + b["t_count"][i]]
+        assert np.all(np.isnan(blk(1))) and np.all(np.isnan(blk(2))) and np.all(np.isnan(blk(3))), prec
+        assert np.all(np.isfinite(blk(0))), prec
+    b["k"][3] = -0.1
     g = _run(pt, b, "ma", "fp32")
-    blk = lambda i: g[b["flux_off"][i]:b["flux_off"][i] + b["t_count"][i]]
-    assert np.all(np.isnan(blk(1))) and np.all(np.isnan(blk(2)))
-    assert np.all(np.isfinite(blk(0))) and np.all(np.isfinite(blk(3)))
+    assert np.all(np.isnan(g[b["flux_off"][3]:b["flux_off"][3] + b["t_count"][3]]))
 
 
 def test_batch_deterministic_and_graph_matches_eager(pt, monkeypatch):
