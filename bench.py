@@ -61,8 +61,11 @@ def parse():
     ap.add_argument("--mode", choices=("full", "kernel", "units"), default="full",
                     help="kernel: only the timed batch launches (for profilers); units: divergence-free "
                          "launches of each unit of work, for counting operations per unit")
-    ap.add_argument("--kernel-model", choices=("ma", "ma_interp"), default="ma",
-                    help="model timed by --mode kernel (ma_interp: tables over the batch's k range, 256 x 2048)")
+    ap.add_argument("--kernel-model", choices=("ma", "ma_interp", "gimenez"), default="ma",
+                    help="model timed by --mode kernel (ma_interp: tables over the batch's k range, "
+                         "256 x 2048 nodes; gimenez: npol = 50)")
+    ap.add_argument("--kernel-workload", choices=("long-cadence", "spectrophotometric", "uneven"),
+                    default="long-cadence", help="workload timed by --mode kernel")
     return ap.parse_args()
 
 
@@ -214,17 +217,26 @@ def main():
         unit_probes()
         return
 
+    if args.mode == "kernel" and (args.kernel_model != "ma" or args.kernel_workload != "long-cadence"):
+        # one model on one workload, launches only (for profilers)
+        kb = {"long-cadence": W.config2, "spectrophotometric": W.config3, "uneven": W.config4}[args.kernel_workload]()
+        u = None
+        if args.kernel_model == "gimenez":
+            u = np.stack([kb["u"][:, 0] + 2 * kb["u"][:, 1], -kb["u"][:, 1]], 1)
+        kdb = pthip.DeviceBatch(kb, u=u)
+        kflux = torch.empty(kb["n_flux"], dtype=torch.float32, device="cuda")
+        if args.kernel_model == "ma_interp":
+            pthip.ma_table_set(float(kb["k"].min()), float(kb["k"].max()), 256, 2048)
+        step = lambda: pthip.lc_batch(kdb, args.kernel_model, npol=50, prec="fp32", out=kflux)
+        wall, _ = timed(step, args.steps, args.warmup)
+        print(json.dumps({"mode": "kernel", "model": args.kernel_model, "workload": kb["name"],
+                          "ms_per_step": wall / args.steps * 1e3,
+                          "points_per_s": W.n_points(kb) * args.steps / wall}), flush=True)
+        return
     batch = W.config2()
     db = pthip.DeviceBatch(batch)
     points = W.n_points(batch)
     flux = torch.empty(batch["n_flux"], dtype=torch.float32, device="cuda")
-    if args.mode == "kernel" and args.kernel_model == "ma_interp":
-        pthip.ma_table_set(float(batch["k"].min()), float(batch["k"].max()), 256, 2048)
-        step = lambda: pthip.lc_batch(db, "ma_interp", prec="fp32", out=flux)
-        wall, _ = timed(step, args.steps, args.warmup)
-        print(json.dumps({"mode": "kernel", "model": "ma_interp", "ms_per_step": wall / args.steps * 1e3,
-                          "points_per_s": points * args.steps / wall}), flush=True)
-        return
     if args.autotune:
         rep = pthip.autotune(db, "ma", prec="fp32", out=flux)
         print(json.dumps({"autotune": rep}), file=sys.stderr, flush=True)

@@ -83,7 +83,7 @@ struct BatchArgs {
   BandConst* bc;        // [n_band], written by the prep kernel
   void* gtab;           // Gimenez per-band tables [n_band][nldc+1][npol] (float or double)
   const void* grec;     // shared recurrence coefficients [(nldc+1)][npol][3]
-  const double* gaprime;  // A'_{n,j} [(nldc+1)][npol]
+  const double4* gbcoef;  // [(nldc+1)][npol] {A_j, B_j, C_j, A'_{n,j}} of the band tables
   unsigned int* queue;  // kQueues counters, kQueueStride apart (reset by the prep kernel)
   void* flux;
   int64_t n_tiles;
@@ -130,7 +130,7 @@ hipError_t launch_orbit_z(const double* t, int64_t n, const OrbitConst& o, int p
 hipError_t launch_ma_quad(const double* z, int64_t n, double k, const double* u, int nb, int prec,
                           double* flux, hipStream_t s);
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
-                             const double* aprime, void* tab, int prec, hipStream_t s);
+                             const double4* bcoef, void* tab, int prec, hipStream_t s);
 hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u, int nldc, int nb,
                           int npol, const void* tab, const void* rec, int prec, double* flux,
                           hipStream_t s);

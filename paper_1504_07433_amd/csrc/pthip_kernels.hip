@@ -114,32 +114,70 @@ hipError_t launch_ma_quad(const double* z, int64_t n, double k, const double* u,
 // ---------------------------------------------------------------------------
 // Gimenez per-band tables: one thread per (band, n).
 // ---------------------------------------------------------------------------
+// One wavefront per 64 table rows (band, n); lane = row.  Row r is written at
+// tab + r * gim_row(npol): the terms go through a 16 x 64 tile in LDS so that
+// each store instruction writes 4 rows x 16 consecutive terms instead of 64
+// scattered words.
+constexpr int kGimTile = 16;
+
 template <class T>
 __global__ __launch_bounds__(256) void k_gim_band_tables(const double* __restrict__ kvec, double kscalar,
                                                          int n_band, int nldc, int npol,
-                                                         const double* __restrict__ aprime,
+                                                         const double4* __restrict__ bcoef,
                                                          T* __restrict__ tab) {
-  const int64_t total = (int64_t)n_band * (nldc + 1);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
-    const int64_t band = id / (nldc + 1);
-    const int n = (int)(id % (nldc + 1));
+  __shared__ T tile[(256 / kWave) * kGimTile * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  T* tl = tile + (threadIdx.x / kWave) * kGimTile * kWave;
+  const int64_t rows = (int64_t)n_band * (nldc + 1);
+  const int row_len = gim_row(npol);
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; w * kWave < rows; w += n_waves) {
+    const int64_t r = w * kWave + lane;
+    const bool live = r < rows;
+    const int64_t band = live ? r / (nldc + 1) : 0;
+    const int n = live ? (int)(r % (nldc + 1)) : 0;
     const double k = kvec ? kvec[band] : kscalar;
-    gimenez_band_table_n<T>(k, n, npol, aprime + (int64_t)n * npol,
-                            tab + (band * (nldc + 1) + n) * (int64_t)gim_row(npol));
+    const double bt = k / (1.0 + k);
+    const double x = 2.0 * bt - 1.0;
+    const double4* __restrict__ cn = bcoef + (int64_t)n * npol;
+    double pm1 = 0.0, p = 1.0;
+    T* out = tab + w * kWave * (int64_t)row_len;     // the wave's 64 rows are contiguous
+    for (int jb = 0; jb < row_len; jb += kGimTile) {
+      const int cl = row_len - jb < kGimTile ? row_len - jb : kGimTile;
+      for (int jl = 0; jl < cl; ++jl) {
+        const int j = jb + jl;
+        T v = T(0);
+        if (j < npol) {       // the b^2 A' P^2 term, then the recurrence to P_{j+1}
+          const double4 c = cn[j];
+          v = T(bt * bt * c.w * p * p);
+          const double pn = (c.x * x + c.y) * p - c.z * pm1;
+          pm1 = p;
+          p = pn;
+        }
+        tl[jl * kWave + lane] = v;
+      }
+      wave_lds_sync();
+      for (int i = 0; i < kGimTile; ++i) {
+        const int e = i * kWave + lane;
+        const int rr = e / kGimTile, jl = e % kGimTile;
+        if (jl < cl && w * kWave + rr < rows) out[(int64_t)rr * row_len + jb + jl] = tl[jl * kWave + rr];
+      }
+      wave_lds_sync();
+    }
   }
 }
 
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
-                             const double* aprime, void* tab, int prec, hipStream_t s) {
+                             const double4* bcoef, void* tab, int prec, hipStream_t s) {
   const int64_t total = (int64_t)n_band * (nldc + 1);
   if (total == 0) return hipSuccess;
+  const int grid = grid_for((total + kWave - 1) / kWave * kWave, 256);
   if (prec == kPrecFP64)
-    hipLaunchKernelGGL(k_gim_band_tables<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, kvec,
-                       kscalar, n_band, nldc, npol, aprime, (double*)tab);
+    hipLaunchKernelGGL(k_gim_band_tables<double>, dim3(grid), dim3(256), 0, s, kvec, kscalar, n_band, nldc,
+                       npol, bcoef, (double*)tab);
   else
-    hipLaunchKernelGGL(k_gim_band_tables<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, kvec,
-                       kscalar, n_band, nldc, npol, aprime, (float*)tab);
+    hipLaunchKernelGGL(k_gim_band_tables<float>, dim3(grid), dim3(256), 0, s, kvec, kscalar, n_band, nldc,
+                       npol, bcoef, (float*)tab);
   return hipGetLastError();
 }
 
@@ -809,7 +847,7 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
-    err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gaprime, a.gtab, prec, s);
+    err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab, prec, s);
     if (err != hipSuccess) return err;
   }
   if (model == kModelMAInterp && a.ltab) {

@@ -103,10 +103,11 @@ struct DevBuf {
   }
 };
 
-// Gimenez k-independent tables for (nldc, npol): A'_{n,j} (double) and the
-// Clenshaw recurrence coefficients {A_j, B_j, C_{j+1}} in float and double.
+// Gimenez k-independent tables for (nldc, npol): the band-table recurrence
+// terms {A_j, B_j, C_j, A'_{n,j}} (double) and the Clenshaw recurrence
+// coefficients {A_j, B_j, C_{j+1}, 0} in float and double.
 struct GimTables {
-  DevBuf aprime, rec32, rec64;
+  DevBuf bcoef, rec32, rec64;
 };
 static std::map<std::tuple<int, int, int>, std::unique_ptr<GimTables>> g_gim;
 
@@ -121,11 +122,14 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
   const size_t nn = (size_t)(nldc + 1) * npol;
   const int row = gim_row(npol);
   const size_t nr = (size_t)(nldc + 1) * row * 4;     // {A, B, C, 0} per padded term
-  std::vector<double> ap(nn), r64(nr, 0.0);
+  std::vector<double> r64(nr, 0.0);
+  std::vector<double4> bc(nn);
   std::vector<float> r32(nr, 0.0f);
   for (int n = 0; n <= nldc; ++n)
     for (int j = 0; j < npol; ++j) {
-      ap[n * npol + j] = gimenez_aprime(n, j);
+      double bA, bB, bC;
+      jacobi_coef(j, 0.5 * (n + 2), 1.0, &bA, &bB, &bC);   // P^(nu,1) of the band tables
+      bc[n * npol + j] = make_double4(bA, bB, bC, gimenez_aprime(n, j));
       double A, B, Cn;
       gimenez_rec_coef(n, j, &A, &B, &Cn);
       const size_t o = 4 * ((size_t)n * row + j);
@@ -133,10 +137,10 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
       r32[o] = float(A); r32[o + 1] = float(B); r32[o + 2] = float(Cn);
     }
   auto t = std::make_unique<GimTables>();
-  PT_HIP(t->aprime.ensure(nn * sizeof(double)));
+  PT_HIP(t->bcoef.ensure(nn * sizeof(double4)));
   PT_HIP(t->rec64.ensure(nr * sizeof(double)));
   PT_HIP(t->rec32.ensure(nr * sizeof(float)));
-  PT_HIP(hipMemcpy(t->aprime.p, ap.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+  PT_HIP(hipMemcpy(t->bcoef.p, bc.data(), nn * sizeof(double4), hipMemcpyHostToDevice));
   PT_HIP(hipMemcpy(t->rec64.p, r64.data(), nr * sizeof(double), hipMemcpyHostToDevice));
   PT_HIP(hipMemcpy(t->rec32.p, r32.data(), nr * sizeof(float), hipMemcpyHostToDevice));
   *out = t.get();
@@ -477,7 +481,7 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     if (st != PT_OK) return st;
     a->gtab = p->gtab.p;
     a->grec = p->prec == PT_PREC_FP64 ? g->rec64.p : g->rec32.p;
-    a->gaprime = (const double*)g->aprime.p;
+    a->gbcoef = (const double4*)g->bcoef.p;
   }
   return PT_OK;
 }
@@ -602,7 +606,7 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
   void* tab = nullptr;
   const size_t bytes = (size_t)(nldc + 1) * gim_row(npol) * (pr == kPrecFP64 ? 8 : 4);
   PT_HIP(hipMallocAsync(&tab, bytes, s));
-  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double*)g->aprime.p, tab, pr, s);
+  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double4*)g->bcoef.p, tab, pr, s);
   hipError_t e2 = e1 == hipSuccess
                       ? launch_gimenez(z, n, k, u, nldc, nb, npol, tab,
                                        pr == kPrecFP64 ? g->rec64.p : g->rec32.p, pr, flux, s)

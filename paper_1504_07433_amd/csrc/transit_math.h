@@ -677,6 +677,23 @@ PT_HD void gimenez_band_table_n(double k, int n, int npol, const double* aprime_
   }
 }
 
+// The same row from precomputed k-independent terms: coef_n[j] =
+// {A_j, B_j, C_j, A'_{n,j}} of P_{j+1}^(nu,1)(x) = (A_j x + B_j) P_j - C_j P_{j-1}.
+template <class T>
+PT_HD void gimenez_band_table_pre(double k, int npol, const double4* coef_n, T* out_n) {
+  for (int j = npol; j < gim_row(npol); ++j) out_n[j] = T(0);
+  const double bt = k / (1.0 + k);
+  const double x = 2.0 * bt - 1.0;
+  double pm1 = 0.0, p = 1.0;
+  for (int j = 0; j < npol; ++j) {
+    const double4 c = coef_n[j];
+    out_n[j] = T(bt * bt * c.w * p * p);
+    const double pn = (c.x * x + c.y) * p - c.z * pm1;
+    pm1 = p;
+    p = pn;
+  }
+}
+
 // All n = 0..nldc, written as T[n * gim_row(npol) + j].
 template <class T>
 PT_HD void gimenez_band_table(double k, int nldc, int npol, const double* aprime, T* out) {
