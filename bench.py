@@ -207,8 +207,8 @@ def sampled_error(pt, O, batch, flux, n=2000, model=0, npol=50, u=None, seed=0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   f"(got {args.gpus}); see the sharding notes in DESIGN.md"}))
+        print(json.dumps({"error": "the transit-model path runs on one GPU only; --gpus must be 1 "
+                                   f"(got {args.gpus})"}))
         sys.exit(2)
     import torch
     from paper_1504_07433_amd import pthip, workloads as W

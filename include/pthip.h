@@ -39,7 +39,7 @@ typedef enum {
   PT_ERR_ARG = 1,          /* invalid argument (message names it)          */
   PT_ERR_HIP = 2,          /* a HIP runtime call failed                    */
   PT_ERR_NOMEM = 3,        /* device or host allocation failed             */
-  PT_ERR_UNSUPPORTED = 4   /* valid request this build does not provide    */
+  PT_ERR_UNSUPPORTED = 4   /* valid request this library does not provide  */
 } pt_status;
 
 typedef enum {

@@ -336,9 +336,18 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
       o.cut_lo = -1e300;
       o.cut_hi = 1e300;
     }
+    // Per-exposure position series for the float path: the smallest
+    // truncation bound over 64 radii of the analytic strip, one per lane.
+    const int nss = a.nss[lc];
+    const double dmax = 2.0 * kPi * o.inv_p * a.t_exp[lc] * (0.5 - 0.5 / nss) + 1e-6;
+    const double rho = o.e > 0.0 && o.e < 1.0 ? acosh(1.0 / o.e) - sqrt(1.0 - o.e * o.e) : 4.0;
+    double rem = orbit_series_bound(o, dmax, fmin(rho, 4.0) * (lane + 1) / (kWave + 1));
+    for (int off = 32; off > 0; off >>= 1) rem = fmin(rem, __shfl_xor(rem, off));
     if (lane == 0) {
       a.oc[lc] = o;
-      a.ocf[lc] = orbit_f(o);
+      OrbitF f = orbit_f(o);
+      f.series = o.valid && nss >= kOrbitSeriesMinSubsamples && rem <= kOrbitSeriesTol;
+      a.ocf[lc] = f;
       if (a.khat) a.khat[lc] = b1 > b0 ? ks / (b1 - b0) : 0.0;
     }
   }
@@ -675,35 +684,45 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
       return 2.0 * kPi * (ph - rint(ph));
     };
 
-    // z for subsamples s0 .. s0+ns-1 of this lane's exposure into LDS
-    auto orbit_chunk = [&](double tm, double dmid, int s0, int ns) {
-      float dm_hi = 0.0f, dm_lo = 0.0f;
+    // z of subsample s of this chunk into LDS
+    auto put_z = [&](int s, T z) {
+      if (!orbit_ok) z = T(NAN);
+      if constexpr (MODEL == kModelMAKhat) {
+        // the functions once per point at the mean radius ratio, shared by the bands
+        MaAlpha<float> r{0.0f, 0.0f, 0.0f};
+        if (z != z) r = MaAlpha<float>{z, z, z};
+        else if (z >= 0.0f && z < khat_onepk) r = ma_alpha_fast(z, khat_f, khat, khat > 0.5, khat_omk);
+        zb[s * kWave + lane] = r.le;
+        zb[(kZChunk + s) * kWave + lane] = r.ld;
+        zb[(2 * kZChunk + s) * kWave + lane] = r.ed;
+      } else {
+        zb[s * kWave + lane] = z;
+      }
+    };
+    // z for subsamples s0 .. s0+ns-1 of this lane's exposure into LDS; the
+    // position series only where the chunk is the whole exposure (in the
+    // per-band loop its coefficients would stay live across the model)
+    auto orbit_chunk = [&](double tm, double dmid, int s0, int ns, bool whole) {
       if constexpr (F32) {
         // dM at the exposure centre split into two floats
-        dm_hi = float(dmid);
-        dm_lo = float(dmid - double(dm_hi));
-      }
-      for (int s = 0; s < ns; ++s) {
-        T z;
-        if constexpr (F32) {
-          const float off = fmaf(step_f, float(s0 + s), base_f);
-          const float dm = dm_hi + (dm_lo + off);
-          z = (dm < of.cut_lo || dm > of.cut_hi) ? far_out : orbit_zf(of, dm);
+        const float dm_hi = float(dmid);
+        const float dm_lo = float(dmid - double(dm_hi));
+        if (whole && of.series) {
+          // one solve at the centre, the subsamples from the position series
+          float px[kOrbitSeries + 1], py[kOrbitSeries + 1];
+          orbit_series(of, dm_hi, px, py);
+          for (int s = 0; s < ns; ++s)
+            put_z(s, orbit_series_z(px, py, of.ycs, dm_lo + fmaf(step_f, float(s0 + s), base_f)));
         } else {
-          const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
-          z = orbit_z_from_dm<T, true>(oc, T(mean_anomaly_offset(oc, ts)), far_out);
+          for (int s = 0; s < ns; ++s) {
+            const float dm = dm_hi + (dm_lo + fmaf(step_f, float(s0 + s), base_f));
+            put_z(s, (dm < of.cut_lo || dm > of.cut_hi) ? far_out : orbit_zf(of, dm));
+          }
         }
-        if (!orbit_ok) z = T(NAN);
-        if constexpr (MODEL == kModelMAKhat) {
-          // the functions once per point at the mean radius ratio, shared by the bands
-          MaAlpha<float> r{0.0f, 0.0f, 0.0f};
-          if (z != z) r = MaAlpha<float>{z, z, z};
-          else if (z >= 0.0f && z < khat_onepk) r = ma_alpha_fast(z, khat_f, khat, khat > 0.5, khat_omk);
-          zb[s * kWave + lane] = r.le;
-          zb[(kZChunk + s) * kWave + lane] = r.ld;
-          zb[(2 * kZChunk + s) * kWave + lane] = r.ed;
-        } else {
-          zb[s * kWave + lane] = z;
+      } else {
+        for (int s = 0; s < ns; ++s) {
+          const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
+          put_z(s, orbit_z_from_dm<T, true>(oc, T(mean_anomaly_offset(oc, ts)), far_out));
         }
       }
     };
@@ -735,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
       }
       if (nss <= kZChunk) {
         // one orbit solve per (exposure, subsample), shared by every band
-        orbit_chunk(tm, dmid, 0, nss);
+        orbit_chunk(tm, dmid, 0, nss, true);
         for (int bnd = b0; bnd < b1; ++bnd) {
           // band constants once per band, by scalar loads
           const BandConst bcv = load_uniform(a.bc + bnd);
@@ -749,7 +768,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
           T acc = T(0);
           for (int s0 = 0; s0 < nss; s0 += kZChunk) {
             const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
-            orbit_chunk(tm, dmid, s0, ns);
+            orbit_chunk(tm, dmid, s0, ns, false);
             acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride, grec, act);
           }
           finish(acc, bcv, bnd, i, act_lane);

@@ -54,10 +54,6 @@ template <> struct Num<float> {
     return 1.0f / x;
 #endif
   }
-  // atan2 for y >= 0 (upper half plane): t = min(|x|, y) / max(|x|, y) in
-  // [0, 1], atan t by an odd polynomial of degree 17 whose coefficients were
-  // fitted to atan on [0, 1] by Lawson's iteratively reweighted least squares
-  // (maximum error 5.8e-9), then the octant is restored.
   PT_HD static float rsqrt(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
     return __builtin_amdgcn_rsqf(x);
@@ -65,6 +61,10 @@ template <> struct Num<float> {
     return 1.0f / ::sqrtf(x);
 #endif
   }
+  // atan2 for y >= 0 (upper half plane): t = min(|x|, y) / max(|x|, y) in
+  // [0, 1], atan t by an odd polynomial of degree 17 whose coefficients were
+  // fitted to atan on [0, 1] by Lawson's iteratively reweighted least squares
+  // (maximum error 5.8e-9), then the octant is restored.
   PT_HD static float atan2(float y, float x) {
     const float ax = fabsf(x);
     const float lo = fminf(ax, y), hi = fmaxf(ax, y);
@@ -392,6 +392,7 @@ struct OrbitF {
   float sx, vx, y0, sy, vy, ycs;
   float cut_lo, cut_hi;   // in-transit window of dM (float, widened)
   int32_t circular, valid;
+  int32_t series;         // subsamples from the position series of their exposure
 };
 
 PT_HD OrbitF orbit_f(const OrbitConst& o) {
@@ -420,13 +421,15 @@ PT_HD OrbitF orbit_f(const OrbitConst& o) {
   f.cut_hi = o.cut_hi > 4.0 ? 1e30f : float(o.cut_hi + 1e-6);
   f.circular = o.circular;
   f.valid = o.valid;
+  f.series = 0;
   return f;
 }
 
-// Signed z in float.  Eccentric orbits: one Halley step from the series
-// starting value, accepted when the step is small enough for the error
-// bound above; otherwise Newton's method continues from there.
-PT_HD float orbit_zf(const OrbitF& o, float dm) {
+// sin x and 1 - cos x of the eccentric-anomaly offset x in float.  Eccentric
+// orbits: one Halley step from the series starting value, accepted when the
+// step is small enough for the error bound above; otherwise Newton's method
+// continues from there.
+PT_HD void orbit_sv(const OrbitF& o, float dm, float* s_out, float* v_out) {
   float s, v;
   if (o.circular) {
     sin_vers(dm, &s, &v);
@@ -447,11 +450,112 @@ PT_HD float orbit_zf(const OrbitF& o, float dm) {
     }
     if (!ok) kepler_newton<float>(o.e, o.ec, o.es, dm, x == x ? x : y, &s, &v);
   }
+  *s_out = s;
+  *v_out = v;
+}
+
+// Signed z in float.
+PT_HD float orbit_zf(const OrbitF& o, float dm) {
+  float s, v;
+  orbit_sv(o, dm, &s, &v);
   const float X = o.sx * s + o.vx * v;
   const float Y = o.y0 + o.sy * s + o.vy * v;
   const float Yc = Y * o.ycs;
   const float z = Num<float>::sqrt(X * X + Yc * Yc);
   return Y < 0.0f ? -z : z;
+}
+
+// ---------------------------------------------------------------------------
+// Sky position of the subsamples of one exposure as power series in the
+// mean-anomaly offset d from the exposure's centre (Sect. 2.1.3 solves
+// Kepler's equation once per subsample; this solves it once per exposure).
+// With x(d) the eccentric-anomaly offset from conjunction, S = sin x and
+// C = cos x, Kepler's equation reads x - e cos E_c S + e sin E_c (1 - C) = dM.
+// From S' = C x' and C' = -S x' the coefficients obey, for j >= 1,
+//   S_j = x_j C_0 + A_j,  A_j = (1/j) sum_{m<j} m x_m C_{j-m},
+//   C_j = -x_j S_0 + B_j, B_j = -(1/j) sum_{m<j} m x_m S_{j-m},
+//   x_j (1 - e cos E) = [j = 1] + e cos E_c A_j + e sin E_c B_j,
+// with E the eccentric anomaly at the centre; X' and Y are linear in S and
+// 1 - C.  One solve, one reciprocal and ~100 operations per exposure, then
+// 2 kOrbitSeries FMAs per subsample.
+// ---------------------------------------------------------------------------
+constexpr int kOrbitSeries = 6;
+constexpr double kOrbitSeriesTol = 3e-8;      // truncation bound on z
+constexpr int kOrbitSeriesMinSubsamples = 4;  // below this one solve per subsample is cheaper
+
+PT_HD void orbit_series(const OrbitF& o, float dm, float* px, float* py) {
+  float s, v;
+  orbit_sv(o, dm, &s, &v);
+  const float c0 = 1.0f - v;
+  const float q = Num<float>::rcp(1.0f - o.ec * c0 + o.es * s);
+  float mx[kOrbitSeries + 1], S[kOrbitSeries + 1], C[kOrbitSeries + 1];
+  S[0] = s;
+  C[0] = c0;
+  mx[0] = 0.0f;
+#pragma unroll
+  for (int j = 1; j <= kOrbitSeries; ++j) {
+    float A = 0.0f, B = 0.0f;
+#pragma unroll
+    for (int m = 1; m < j; ++m) {
+      A = fmaf(mx[m], C[j - m], A);
+      B = fmaf(-mx[m], S[j - m], B);
+    }
+    const float inv_j = 1.0f / float(j);
+    A *= inv_j;
+    B *= inv_j;
+    const float xj = ((j == 1 ? 1.0f : 0.0f) + o.ec * A + o.es * B) * q;
+    mx[j] = float(j) * xj;
+    S[j] = fmaf(xj, c0, A);
+    C[j] = fmaf(-xj, s, B);
+  }
+  px[0] = o.sx * s + o.vx * v;
+  py[0] = o.y0 + o.sy * s + o.vy * v;
+#pragma unroll
+  for (int j = 1; j <= kOrbitSeries; ++j) {
+    px[j] = o.sx * S[j] - o.vx * C[j];
+    py[j] = o.sy * S[j] - o.vy * C[j];
+  }
+}
+
+// Signed z at offset d from the expansion point.
+PT_HD float orbit_series_z(const float* px, const float* py, float ycs, float d) {
+  float X = px[kOrbitSeries], Y = py[kOrbitSeries];
+#pragma unroll
+  for (int j = kOrbitSeries - 1; j >= 0; --j) {
+    X = fmaf(X, d, px[j]);
+    Y = fmaf(Y, d, py[j]);
+  }
+  const float Yc = Y * ycs;
+  const float z = Num<float>::sqrt(X * X + Yc * Yc);
+  return Y < 0.0f ? -z : z;
+}
+
+// Bound on |z - series z| for |d| <= dmax from Cauchy's estimate on the circle
+// |d| = r.  E(M) is analytic for |Im M| < rho_e = acosh(1/e) - sqrt(1 - e^2)
+// (Kepler's equation branches where e cos E = 1), and there |Im E| <= t with
+// t - e sinh t = |Im M| (t - e sinh t increases up to acosh(1/e)).  Then
+// |cos E - cos E_c| and |sin E - sin E_c| stay below cosh t + 1, so X' and
+// Y cos i a/R* - const are below B = sqrt(2) a/R* (cosh t + 1), and each
+// remainder below B (dmax/r)^(N+1) / (1 - dmax/r).  Returns 1e300 when r is
+// not inside the analytic strip or not beyond dmax.
+PT_HD double orbit_series_bound(const OrbitConst& o, double dmax, double r) {
+  const double e = o.e;
+  if (!(r > dmax) || !(e >= 0.0 && e < 1.0)) return 1e300;
+  double t = r;
+  if (e > 0.0) {
+    const double tmax = ::acosh(1.0 / e);
+    if (!(r < tmax - ::sqrt(1.0 - e * e))) return 1e300;
+    double lo = 0.0, hi = tmax;                // g(lo) < r <= g(hi)
+    for (int it = 0; it < 40; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid - e * ::sinh(mid) < r) lo = mid;
+      else hi = mid;
+    }
+    t = hi;                                    // an upper bound of g^-1(r)
+  }
+  const double B = 1.4142135623730951 * o.aR * (::cosh(t) + 1.0);
+  const double x = dmax / r;
+  return 1.4142135623730951 * B * ::pow(x, double(kOrbitSeries + 1)) / (1.0 - x);
 }
 
 // ---------------------------------------------------------------------------

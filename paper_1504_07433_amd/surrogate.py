@@ -1,4 +1,4 @@
-"""Training driver of the learned surrogate (row "surrogate" of the hot path).
+"""Training driver of the learned surrogate of the Mandel & Agol functions.
 
 The network maps (z, k) to the three limb-darkening-factored Mandel & Agol
 functions.  Every arithmetic step runs in libpthip.so: exact targets
