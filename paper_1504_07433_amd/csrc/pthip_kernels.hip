@@ -684,20 +684,20 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
       return 2.0 * kPi * (ph - rint(ph));
     };
 
+    // the functions once per point at the mean radius ratio, shared by the
+    // bands (k-hat model): three LDS planes
+    auto khat_planes = [&](int s, float z) {
+      MaAlpha<float> r{0.0f, 0.0f, 0.0f};
+      if (z != z) r = MaAlpha<float>{z, z, z};
+      else if (z >= 0.0f && z < khat_onepk) r = ma_alpha_fast(z, khat_f, khat, khat > 0.5, khat_omk);
+      zb[s * kWave + lane] = r.le;
+      zb[(kZChunk + s) * kWave + lane] = r.ld;
+      zb[(2 * kZChunk + s) * kWave + lane] = r.ed;
+    };
     // z of subsample s of this chunk into LDS
     auto put_z = [&](int s, T z) {
-      if (!orbit_ok) z = T(NAN);
-      if constexpr (MODEL == kModelMAKhat) {
-        // the functions once per point at the mean radius ratio, shared by the bands
-        MaAlpha<float> r{0.0f, 0.0f, 0.0f};
-        if (z != z) r = MaAlpha<float>{z, z, z};
-        else if (z >= 0.0f && z < khat_onepk) r = ma_alpha_fast(z, khat_f, khat, khat > 0.5, khat_omk);
-        zb[s * kWave + lane] = r.le;
-        zb[(kZChunk + s) * kWave + lane] = r.ld;
-        zb[(2 * kZChunk + s) * kWave + lane] = r.ed;
-      } else {
-        zb[s * kWave + lane] = z;
-      }
+      if constexpr (MODEL == kModelMAKhat) khat_planes(s, z);
+      else zb[s * kWave + lane] = z;
     };
     // z for subsamples s0 .. s0+ns-1 of this lane's exposure into LDS; the
     // position series only where the chunk is the whole exposure (in the
@@ -709,27 +709,37 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
         const float dm_lo = float(dmid - double(dm_hi));
         if (whole && of.series) {
           // one solve at the centre, the subsamples from the position series
+          // (an invalid orbit gives NaN through the constant term)
           float px[kOrbitSeries + 1], py[kOrbitSeries + 1];
           orbit_series(of, dm_hi, px, py);
+          if (!orbit_ok) px[0] = NAN;
+          const float d0 = dm_lo + base_f;
           for (int s = 0; s < ns; ++s)
-            put_z(s, orbit_series_z(px, py, of.ycs, dm_lo + fmaf(step_f, float(s0 + s), base_f)));
+            zb[s * kWave + lane] = orbit_series_z(px, py, of.ycs, fmaf(step_f, float(s0 + s), d0));
+          // the k-hat functions after the series, so that its coefficients
+          // are not live across them
+          if constexpr (MODEL == kModelMAKhat)
+            for (int s = 0; s < ns; ++s) khat_planes(s, zb[s * kWave + lane]);
         } else {
           for (int s = 0; s < ns; ++s) {
             const float dm = dm_hi + (dm_lo + fmaf(step_f, float(s0 + s), base_f));
-            put_z(s, (dm < of.cut_lo || dm > of.cut_hi) ? far_out : orbit_zf(of, dm));
+            const float z = (dm < of.cut_lo || dm > of.cut_hi) ? far_out : orbit_zf(of, dm);
+            put_z(s, orbit_ok ? z : NAN);
           }
         }
       } else {
         for (int s = 0; s < ns; ++s) {
           const double ts = tm + texp * ((s0 + s + 0.5) * inv_nss - 0.5);
-          put_z(s, orbit_z_from_dm<T, true>(oc, T(mean_anomaly_offset(oc, ts)), far_out));
+          const T z = orbit_z_from_dm<T, true>(oc, T(mean_anomaly_offset(oc, ts)), far_out);
+          put_z(s, orbit_ok ? z : T(NAN));
         }
       }
     };
     auto finish = [&](T acc, const BandConst& bcv, int bnd, int i, bool act_lane) {
       if constexpr (MODEL == kModelMAKhat) acc *= T(bcv.kf * bcv.kf * inv_khat2);
-      // a band whose radius ratio is not positive and finite gives NaN throughout
-      const T f = bcv.valid ? T(1) - acc * T(inv_nss) : T(NAN);
+      // a band whose radius ratio is not positive and finite, or an orbit
+      // that is not valid, gives NaN throughout (whatever the model made of z)
+      const T f = bcv.valid && orbit_ok ? T(1) - acc * T(inv_nss) : T(NAN);
       const int64_t idx = fo + (int64_t)(bnd - b0) * cnt + i;
       if (LOGL) {
         if (act_lane) {

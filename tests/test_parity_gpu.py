@@ -278,6 +278,18 @@ def test_batch_nonphysical_parameters_give_nan(pt):
     b["k"][3] = -0.1
     g = _run(pt, b, "ma", "fp32")
     assert np.all(np.isnan(g[b["flux_off"][3]:b["flux_off"][3] + b["t_count"][3]]))
+    # the model variants too: NaN throughout for an invalid orbit or band,
+    # whatever the variant's own handling of z
+    b["k"][3] = np.nan
+    ks = b["k"][np.isfinite(b["k"])]
+    pt.ma_table_set(float(ks.min()), float(ks.max()), 16, 256)
+    pt.gimenez_zgrid_set(64, 64)
+    for model, prec in (("ma_interp", "fp32"), ("ma_khat", "fp32"), ("gimenez", "fp32"), ("gimenez", "fp64"),
+                        ("gimenez_zinterp", "fp32")):
+        g = _run(pt, b, model, prec, npol=20)
+        blk = lambda i: g[b["flux_off"][i]:b["flux_off"][i] + b["t_count"][i]]
+        assert np.all(np.isnan(blk(1))) and np.all(np.isnan(blk(2))) and np.all(np.isnan(blk(3))), model
+        assert np.all(np.isfinite(blk(0))), model
 
 
 def test_batch_deterministic_and_graph_matches_eager(pt, monkeypatch):
