@@ -35,6 +35,16 @@ F_MA_LIMB = 351.4         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8).
 F_POINT, F_EXPOSURE = 5.0, 8.0
+# Light curves with 4..16 subsamples take the orbit from the per-exposure
+# position series.  Their units are measured inside the batch kernel (probes
+# batch-series-4 / -16 / -limb-16, one band, flops per point = A + B / nss):
+# per in-transit point inside the disc or on the limb (series evaluation,
+# Mandel-Agol, limb darkening, accumulation) and per exposure with an
+# in-transit point (phase, one Kepler solve, series coefficients, flux).
+F_SER_INSIDE = 218.6
+F_SER_LIMB = 304.0
+F_SER_EXPOSURE = 300.0
+SERIES_NSS = (4, 16)
 PEAK_ALU = 78.6e12        # 256 CU x 64 FMA lanes x 2 flops x 2.4 GHz (FP32 non-packed = FP64)
 PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second
 HBM_PEAK = 8.0e12
@@ -42,11 +52,11 @@ HBM_PEAK = 8.0e12
 # (profiles/k_lc_batch_fp32_ma_long_cadence_counters.txt): wave64 VALU
 # instructions per launch, and HBM bytes per launch from FETCH_SIZE and
 # WRITE_SIZE (KiB) scaled by what the counters read for an elementwise kernel
-# that reads and writes 1 GiB (FETCH_SIZE reads 524315 KiB for 1 GiB read,
+# that reads and writes 1 GiB (FETCH_SIZE reads 524319 KiB for 1 GiB read,
 # WRITE_SIZE 1048580 KiB for 1 GiB written).
-VALU_INSTS_PER_LAUNCH = 1.12244e9
-FETCH_KIB, WRITE_KIB = 10533.6, 204887.0
-FETCH_SCALE, WRITE_SCALE = 1048576 / 524315, 1.0
+VALU_INSTS_PER_LAUNCH = 1.03897e9
+FETCH_KIB, WRITE_KIB = 10915.0, 204913.0
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524319, 1.0
 
 
 def parse():
@@ -80,21 +90,27 @@ def unit_probes():
       gim-inside  float Gimenez, npol = 50, two coefficients, z in (0, 1-k)
       batch-cut   batch kernel, one light curve whose window holds no point
       batch-in    batch kernel, e = 0.2, every point inside the disc
+      batch-series-4, batch-series-16
+                  the same with 4 / 16 subsamples per exposure (0.01 d), the
+                  orbit from the per-exposure position series
+      batch-series-limb-16
+                  the same with b = 1, every subsample on the limb
     and one elementwise kernel that reads 1 GiB and writes 1 GiB (the
     reference for the HBM byte counters)."""
     import torch
     from paper_1504_07433_amd import pthip, workloads as W
     n = 1 << 24
 
-    def one_lc(b_imp, e, span):
+    def one_lc(b_imp, e, span, nss=1, t_exp=0.0):
+        ne = n // nss
         b = W.config1()
-        b["t"] = np.linspace(-span, span, n)
-        b["t_count"] = np.array([n], np.int64)
-        b["nss"] = np.array([1], np.int32)
-        b["t_exp"] = np.array([0.0])
+        b["t"] = np.linspace(-span, span, ne)
+        b["t_count"] = np.array([ne], np.int64)
+        b["nss"] = np.array([nss], np.int32)
+        b["t_exp"] = np.array([t_exp])
         b["b"] = np.array([b_imp]); b["e"] = np.array([e]); b["w"] = np.array([1.0])
         b["aR"] = np.array([10.0]); b["P"] = np.array([3.0]); b["t0"] = np.array([0.0])
-        b["k"] = np.array([0.1]); b["u"] = np.array([[0.4, 0.2]]); b["n_flux"] = n
+        b["k"] = np.array([0.1]); b["u"] = np.array([[0.4, 0.2]]); b["n_flux"] = ne
         return b
 
     def report(name, out):
@@ -118,7 +134,10 @@ def unit_probes():
         f = pthip.gimenez(zz, 0.1, np.array([[0.8, -0.2]]), npol=50, prec="fp32")
     report("gim-inside", f)
     del zz, f, t, z
-    for name, b in (("batch-cut", one_lc(1.5, 0.0, 0.04)), ("batch-in", one_lc(0.3, 0.2, 0.03))):
+    for name, b in (("batch-cut", one_lc(1.5, 0.0, 0.04)), ("batch-in", one_lc(0.3, 0.2, 0.03)),
+                    ("batch-series-4", one_lc(0.3, 0.2, 0.025, 4, 0.01)),
+                    ("batch-series-16", one_lc(0.3, 0.2, 0.025, 16, 0.01)),
+                    ("batch-series-limb-16", one_lc(1.0, 0.2, 0.01, 16, 0.01))):
         db = pthip.DeviceBatch(b)
         for _ in range(2):
             f = pthip.lc_batch(db, "ma", prec="fp32")
@@ -152,9 +171,11 @@ def count_units(pt, batch):
     """Units of work of one launch, from z on the GPU (pt_orbit_z in FP64 per
     light curve over its subsample times): all orbit points, orbit points in
     transit for some band, and in-transit (band, point) pairs inside the disc
-    and on the limb."""
+    and on the limb; the same for light curves whose orbit comes from the
+    per-exposure series (4..16 subsamples), plus their exposures holding an
+    in-transit point."""
     import torch
-    n_orbit = n_orbit_in = n_inside = n_limb = 0
+    n_orbit = n_orbit_in = n_inside = n_limb = n_series_in = n_series_exp = n_ser_inside = n_ser_limb = 0
     for i in range(len(batch["t_start"])):
         s, c, n = batch["t_start"][i], batch["t_count"][i], int(batch["nss"][i])
         t = torch.as_tensor(batch["t"][s:s + c], device="cuda")
@@ -164,13 +185,26 @@ def count_units(pt, batch):
                        batch["e"][i], batch["w"][i], prec="fp64")
         n_orbit += ts.numel()
         ks = batch["k"][batch["band_off"][i]:batch["band_off"][i + 1]]
-        n_orbit_in += int(((z >= 0) & (z < 1 + float(ks.max()))).sum().item())
+        tr = (z >= 0) & (z < 1 + float(ks.max()))
+        n_tr = int(tr.sum().item())
+        n_orbit_in += n_tr
+        series = SERIES_NSS[0] <= n <= SERIES_NSS[1]
+        if series:
+            n_series_in += n_tr
+            n_series_exp += int(tr.reshape(-1, n).any(dim=1).sum().item())
         for k in ks:
             k = float(k)
-            n_inside += int(((z >= 0) & (z <= 1 - k)).sum().item())
-            n_limb += int(((z > 1 - k) & (z < 1 + k)).sum().item())
+            ni = int(((z >= 0) & (z <= 1 - k)).sum().item())
+            nl = int(((z > 1 - k) & (z < 1 + k)).sum().item())
+            n_inside += ni
+            n_limb += nl
+            if series:
+                n_ser_inside += ni
+                n_ser_limb += nl
     return {"orbit_points": n_orbit, "orbit_points_in_transit": n_orbit_in,
-            "inside_points": n_inside, "limb_points": n_limb}
+            "inside_points": n_inside, "limb_points": n_limb,
+            "series_points_in_transit": n_series_in, "series_exposures_in_transit": n_series_exp,
+            "series_inside_points": n_ser_inside, "series_limb_points": n_ser_limb}
 
 
 def cpu_baseline(batch, seconds):
@@ -253,9 +287,13 @@ def main():
     u = count_units(pthip, batch)
     n_in = u["inside_points"] + u["limb_points"]
     n_exposures = int(batch["t_count"].sum())
-    flops = (u["orbit_points"] * F_POINT + n_exposures * F_EXPOSURE
-             + u["orbit_points_in_transit"] * F_ORBIT_ECC
-             + u["inside_points"] * F_MA_INSIDE + u["limb_points"] * F_MA_LIMB)
+    flops = ((u["orbit_points"] - u["series_points_in_transit"]) * F_POINT
+             + (n_exposures - u["series_exposures_in_transit"]) * F_EXPOSURE
+             + (u["orbit_points_in_transit"] - u["series_points_in_transit"]) * F_ORBIT_ECC
+             + (u["inside_points"] - u["series_inside_points"]) * F_MA_INSIDE
+             + (u["limb_points"] - u["series_limb_points"]) * F_MA_LIMB
+             + u["series_inside_points"] * F_SER_INSIDE + u["series_limb_points"] * F_SER_LIMB
+             + u["series_exposures_in_transit"] * F_SER_EXPOSURE)
     achieved = flops / kernel_s
     hbm = (batch["t"].nbytes + batch["n_flux"] * 4 + 256 * 8 * 8)
     traffic = None

@@ -337,11 +337,11 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
       o.cut_hi = 1e300;
     }
     // Per-exposure position series for the float path: the smallest
-    // truncation bound over 64 radii of the analytic strip, one per lane.
+    // truncation bound over 64 circles inside the analytic strip, one per lane.
     const int nss = a.nss[lc];
     const double dmax = 2.0 * kPi * o.inv_p * a.t_exp[lc] * (0.5 - 0.5 / nss) + 1e-6;
-    const double rho = o.e > 0.0 && o.e < 1.0 ? acosh(1.0 / o.e) - sqrt(1.0 - o.e * o.e) : 4.0;
-    double rem = orbit_series_bound(o, dmax, fmin(rho, 4.0) * (lane + 1) / (kWave + 1));
+    const double tcap = o.e > 0.0 && o.e < 1.0 ? acosh(1.0 / o.e) : 8.0;
+    double rem = orbit_series_bound(o, dmax, tcap * (lane + 1) / (kWave + 1));
     for (int off = 32; off > 0; off >>= 1) rem = fmin(rem, __shfl_xor(rem, off));
     if (lane == 0) {
       a.oc[lc] = o;

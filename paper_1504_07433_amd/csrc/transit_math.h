@@ -384,6 +384,22 @@ PT_HD T orbit_z_from_dm(const OrbitConst& o, T dm, T big_out) {
 // Float form of the orbit constants for the bulk path: the sky position is
 // folded into X' = (a/R*) X = sx sin x + vx (1 - cos x) and
 // Y = y0 + sy sin x + vy (1 - cos x), Y cos i (a/R*) = Y ycs.
+// Sky-position constants of the conjunction frame, computed in double.
+template <class T> struct OrbitFold { T sx, vx, y0, sy, vy, ycs; };
+
+template <class T>
+PT_HD OrbitFold<T> orbit_fold(const OrbitConst& o) {
+  const double sq = o.sq1me2;
+  OrbitFold<T> f;
+  f.sx = T(o.aR * (-o.cw * o.sEc - o.sw * sq * o.cEc));
+  f.vx = T(o.aR * (-o.cw * o.cEc + o.sw * sq * o.sEc));
+  f.y0 = T(o.rc);
+  f.sy = T(-o.sw * o.sEc + o.cw * sq * o.cEc);
+  f.vy = T(-o.sw * o.cEc - o.cw * sq * o.sEc);
+  f.ycs = T(o.aR * o.cos_i);
+  return f;
+}
+
 struct OrbitF {
   double t0, inv_p;       // phase in double
   float e, ec, es;        // e, e cos E_c, e sin E_c
@@ -409,13 +425,13 @@ PT_HD OrbitF orbit_f(const OrbitConst& o) {
   // after a step of size h from an error ~h the error is below K h^3.
   const double K = o.e / (6.0 * (1.0 - o.e)) + o.e * o.e / (4.0 * (1.0 - o.e) * (1.0 - o.e));
   f.halley_ok = K > 0.0 ? float(::cbrt(5e-10 / K)) : 0.0f;
-  const double sq = o.sq1me2;
-  f.sx = float(o.aR * (-o.cw * o.sEc - o.sw * sq * o.cEc));
-  f.vx = float(o.aR * (-o.cw * o.cEc + o.sw * sq * o.sEc));
-  f.y0 = float(o.rc);
-  f.sy = float(-o.sw * o.sEc + o.cw * sq * o.cEc);
-  f.vy = float(-o.sw * o.cEc - o.cw * sq * o.sEc);
-  f.ycs = float(o.aR * o.cos_i);
+  const OrbitFold<float> fold = orbit_fold<float>(o);
+  f.sx = fold.sx;
+  f.vx = fold.vx;
+  f.y0 = fold.y0;
+  f.sy = fold.sy;
+  f.vy = fold.vy;
+  f.ycs = fold.ycs;
   // float rounding of dM is below 3e-7 for |dM| <= 4: widen by 1e-6
   f.cut_lo = o.cut_lo < -4.0 ? -1e30f : float(o.cut_lo - 1e-6);
   f.cut_hi = o.cut_hi > 4.0 ? 1e30f : float(o.cut_hi + 1e-6);
@@ -483,76 +499,87 @@ constexpr int kOrbitSeries = 6;
 constexpr double kOrbitSeriesTol = 3e-8;      // truncation bound on z
 constexpr int kOrbitSeriesMinSubsamples = 4;  // below this one solve per subsample is cheaper
 
+PT_HD float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+PT_HD double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
+// Coefficients of X' and Y from sin x, 1 - cos x at the expansion point
+// (ec = e cos E_c, es = e sin E_c).
+template <class T>
+PT_HD void orbit_series_coef(T ec, T es, const OrbitFold<T>& f, T s, T v, T* px, T* py) {
+  const T c0 = T(1) - v;
+  const T q = Num<T>::rcp(T(1) - ec * c0 + es * s);
+  T mx[kOrbitSeries + 1], S[kOrbitSeries + 1], C[kOrbitSeries + 1];
+  S[0] = s;
+  C[0] = c0;
+  mx[0] = T(0);
+#pragma unroll
+  for (int j = 1; j <= kOrbitSeries; ++j) {
+    T A = T(0), B = T(0);
+#pragma unroll
+    for (int m = 1; m < j; ++m) {
+      A = fma_t(mx[m], C[j - m], A);
+      B = fma_t(-mx[m], S[j - m], B);
+    }
+    const T inv_j = T(1) / T(j);
+    A *= inv_j;
+    B *= inv_j;
+    const T xj = ((j == 1 ? T(1) : T(0)) + ec * A + es * B) * q;
+    mx[j] = T(j) * xj;
+    S[j] = fma_t(xj, c0, A);
+    C[j] = fma_t(-xj, s, B);
+  }
+  px[0] = f.sx * s + f.vx * v;
+  py[0] = f.y0 + f.sy * s + f.vy * v;
+#pragma unroll
+  for (int j = 1; j <= kOrbitSeries; ++j) {
+    px[j] = f.sx * S[j] - f.vx * C[j];
+    py[j] = f.sy * S[j] - f.vy * C[j];
+  }
+}
+
 PT_HD void orbit_series(const OrbitF& o, float dm, float* px, float* py) {
   float s, v;
   orbit_sv(o, dm, &s, &v);
-  const float c0 = 1.0f - v;
-  const float q = Num<float>::rcp(1.0f - o.ec * c0 + o.es * s);
-  float mx[kOrbitSeries + 1], S[kOrbitSeries + 1], C[kOrbitSeries + 1];
-  S[0] = s;
-  C[0] = c0;
-  mx[0] = 0.0f;
-#pragma unroll
-  for (int j = 1; j <= kOrbitSeries; ++j) {
-    float A = 0.0f, B = 0.0f;
-#pragma unroll
-    for (int m = 1; m < j; ++m) {
-      A = fmaf(mx[m], C[j - m], A);
-      B = fmaf(-mx[m], S[j - m], B);
-    }
-    const float inv_j = 1.0f / float(j);
-    A *= inv_j;
-    B *= inv_j;
-    const float xj = ((j == 1 ? 1.0f : 0.0f) + o.ec * A + o.es * B) * q;
-    mx[j] = float(j) * xj;
-    S[j] = fmaf(xj, c0, A);
-    C[j] = fmaf(-xj, s, B);
-  }
-  px[0] = o.sx * s + o.vx * v;
-  py[0] = o.y0 + o.sy * s + o.vy * v;
-#pragma unroll
-  for (int j = 1; j <= kOrbitSeries; ++j) {
-    px[j] = o.sx * S[j] - o.vx * C[j];
-    py[j] = o.sy * S[j] - o.vy * C[j];
-  }
+  OrbitFold<float> f;
+  f.sx = o.sx;
+  f.vx = o.vx;
+  f.y0 = o.y0;
+  f.sy = o.sy;
+  f.vy = o.vy;
+  f.ycs = o.ycs;
+  orbit_series_coef<float>(o.ec, o.es, f, s, v, px, py);
 }
 
 // Signed z at offset d from the expansion point.
-PT_HD float orbit_series_z(const float* px, const float* py, float ycs, float d) {
-  float X = px[kOrbitSeries], Y = py[kOrbitSeries];
+template <class T>
+PT_HD T orbit_series_z(const T* px, const T* py, T ycs, T d) {
+  T X = px[kOrbitSeries], Y = py[kOrbitSeries];
 #pragma unroll
   for (int j = kOrbitSeries - 1; j >= 0; --j) {
-    X = fmaf(X, d, px[j]);
-    Y = fmaf(Y, d, py[j]);
+    X = fma_t(X, d, px[j]);
+    Y = fma_t(Y, d, py[j]);
   }
-  const float Yc = Y * ycs;
-  const float z = Num<float>::sqrt(X * X + Yc * Yc);
-  return Y < 0.0f ? -z : z;
+  const T Yc = Y * ycs;
+  const T z = Num<T>::sqrt(X * X + Yc * Yc);
+  return Y < T(0) ? -z : z;
 }
 
-// Bound on |z - series z| for |d| <= dmax from Cauchy's estimate on the circle
+// Bound on |z - series z| for |d| <= dmax from Cauchy's estimate on a circle
 // |d| = r.  E(M) is analytic for |Im M| < rho_e = acosh(1/e) - sqrt(1 - e^2)
-// (Kepler's equation branches where e cos E = 1), and there |Im E| <= t with
-// t - e sinh t = |Im M| (t - e sinh t increases up to acosh(1/e)).  Then
-// |cos E - cos E_c| and |sin E - sin E_c| stay below cosh t + 1, so X' and
-// Y cos i a/R* - const are below B = sqrt(2) a/R* (cosh t + 1), and each
-// remainder below B (dmax/r)^(N+1) / (1 - dmax/r).  Returns 1e300 when r is
-// not inside the analytic strip or not beyond dmax.
-PT_HD double orbit_series_bound(const OrbitConst& o, double dmax, double r) {
+// (Kepler's equation branches where e cos E = 1).  g(t) = t - e sinh t
+// increases on [0, acosh(1/e)], and |Im M| >= g(|Im E|), so on the disc
+// |d| <= r = g(t) the imaginary part of E stays below t.  Then
+// |cos E - cos E_c| and |sin E - sin E_c| stay below cosh t + 1, X' and
+// Y cos i a/R* - const below B = sqrt(2) a/R* (cosh t + 1), and each
+// remainder below B (dmax/r)^(N+1) / (1 - dmax/r); z's below sqrt(2) times
+// that.  The circle is named by t (0 < t < acosh(1/e)), which needs no
+// inversion of g.  Returns 1e300 when t is outside that range or r <= dmax.
+PT_HD double orbit_series_bound(const OrbitConst& o, double dmax, double t) {
   const double e = o.e;
-  if (!(r > dmax) || !(e >= 0.0 && e < 1.0)) return 1e300;
-  double t = r;
-  if (e > 0.0) {
-    const double tmax = ::acosh(1.0 / e);
-    if (!(r < tmax - ::sqrt(1.0 - e * e))) return 1e300;
-    double lo = 0.0, hi = tmax;                // g(lo) < r <= g(hi)
-    for (int it = 0; it < 40; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid - e * ::sinh(mid) < r) lo = mid;
-      else hi = mid;
-    }
-    t = hi;                                    // an upper bound of g^-1(r)
-  }
+  if (!(e >= 0.0 && e < 1.0) || !(t > 0.0)) return 1e300;
+  if (e > 0.0 && !(t < ::acosh(1.0 / e))) return 1e300;
+  const double r = t - e * ::sinh(t);
+  if (!(r > dmax)) return 1e300;
   const double B = 1.4142135623730951 * o.aR * (::cosh(t) + 1.0);
   const double x = dmax / r;
   return 1.4142135623730951 * B * ::pow(x, double(kOrbitSeries + 1)) / (1.0 - x);
