@@ -40,10 +40,12 @@ F_POINT, F_EXPOSURE = 5.0, 8.0
 # batch-series-4 / -16 / -limb-16, one band, flops per point = A + B / nss):
 # per in-transit point inside the disc or on the limb (series evaluation,
 # Mandel-Agol, limb darkening, accumulation) and per exposure with an
-# in-transit point (phase, one Kepler solve, series coefficients, flux).
-F_SER_INSIDE = 218.6
-F_SER_LIMB = 304.0
-F_SER_EXPOSURE = 300.0
+# in-transit point (phase, one Kepler solve, series coefficients, flux).  The
+# probes run at series order 4; order-5 light curves spend ~4 flops more per
+# point and ~20 more per exposure, which the model does not charge.
+F_SER_INSIDE = 210.0
+F_SER_LIMB = 296.0
+F_SER_EXPOSURE = 228.0
 SERIES_NSS = (4, 16)
 PEAK_ALU = 78.6e12        # 256 CU x 64 FMA lanes x 2 flops x 2.4 GHz (FP32 non-packed = FP64)
 PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second
@@ -54,8 +56,8 @@ HBM_PEAK = 8.0e12
 # WRITE_SIZE (KiB) scaled by what the counters read for an elementwise kernel
 # that reads and writes 1 GiB (FETCH_SIZE reads 524319 KiB for 1 GiB read,
 # WRITE_SIZE 1048580 KiB for 1 GiB written).
-VALU_INSTS_PER_LAUNCH = 1.03897e9
-FETCH_KIB, WRITE_KIB = 10915.0, 204913.0
+VALU_INSTS_PER_LAUNCH = 9.88894e8
+FETCH_KIB, WRITE_KIB = 10783.5, 204912.0
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524319, 1.0
 
 

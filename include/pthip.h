@@ -168,6 +168,12 @@ typedef struct {
 /* Supersampled flux of a ragged batch in one persistent fused orbit+flux
  * launch (replayed from a hipGraph after the first call with a given shape).
  * Each output point is the mean over the exposure's subsamples (Sect. 3.2).
+ * The float precisions solve Kepler's equation once per exposure and take
+ * the subsamples' sky positions from power series about its centre where a
+ * rigorous truncation bound keeps z within 3e-8 (4..16 subsamples; otherwise
+ * one solve per subsample); PT_PREC_FP64 solves per subsample.  A light curve
+ * with non-physical orbit parameters, or a band with a radius ratio that is
+ * not positive and finite, gives NaN in every affected output point.
  *   flux    output [n_flux], device: float for PT_PREC_FP32/PT_PREC_SURROGATE,
  *           double for PT_PREC_FP64
  *   npol    Jacobi terms for PT_MODEL_GIMENEZ (1..512), ignored otherwise

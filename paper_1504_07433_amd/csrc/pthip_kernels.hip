@@ -336,17 +336,25 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
       o.cut_lo = -1e300;
       o.cut_hi = 1e300;
     }
-    // Per-exposure position series for the float path: the smallest
-    // truncation bound over 64 circles inside the analytic strip, one per lane.
+    // Per-exposure position series for the float path: for each order the
+    // smallest truncation bound over 64 circles inside the analytic strip
+    // (one per lane); the light curve takes the lowest order that holds.
     const int nss = a.nss[lc];
     const double dmax = 2.0 * kPi * o.inv_p * a.t_exp[lc] * (0.5 - 0.5 / nss) + 1e-6;
     const double tcap = o.e > 0.0 && o.e < 1.0 ? acosh(1.0 / o.e) : 8.0;
-    double rem = orbit_series_bound(o, dmax, tcap * (lane + 1) / (kWave + 1));
-    for (int off = 32; off > 0; off >>= 1) rem = fmin(rem, __shfl_xor(rem, off));
+    double rem[kOrbitSeriesMax - kOrbitSeriesMin + 1];
+    orbit_series_bounds(o, dmax, tcap * (lane + 1) / (kWave + 1), rem);
+    int order = 0;
+#pragma unroll
+    for (int n = kOrbitSeriesMax; n >= kOrbitSeriesMin; --n) {
+      double r = rem[n - kOrbitSeriesMin];
+      for (int off = 32; off > 0; off >>= 1) r = fmin(r, __shfl_xor(r, off));
+      if (r <= kOrbitSeriesTol) order = n;
+    }
     if (lane == 0) {
       a.oc[lc] = o;
       OrbitF f = orbit_f(o);
-      f.series = o.valid && nss >= kOrbitSeriesMinSubsamples && rem <= kOrbitSeriesTol;
+      f.series = o.valid && nss >= kOrbitSeriesMinSubsamples ? order : 0;
       a.ocf[lc] = f;
       if (a.khat) a.khat[lc] = b1 > b0 ? ks / (b1 - b0) : 0.0;
     }
@@ -709,13 +717,21 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
         const float dm_lo = float(dmid - double(dm_hi));
         if (whole && of.series) {
           // one solve at the centre, the subsamples from the position series
-          // (an invalid orbit gives NaN through the constant term)
-          float px[kOrbitSeries + 1], py[kOrbitSeries + 1];
-          orbit_series(of, dm_hi, px, py);
-          if (!orbit_ok) px[0] = NAN;
-          const float d0 = dm_lo + base_f;
-          for (int s = 0; s < ns; ++s)
-            zb[s * kWave + lane] = orbit_series_z(px, py, of.ycs, fmaf(step_f, float(s0 + s), d0));
+          // of the light curve's order (an invalid orbit gives NaN through
+          // the constant term)
+          auto series_chunk = [&](auto order) {
+            constexpr int N = decltype(order)::value;
+            float px[N + 1], py[N + 1];
+            orbit_series<N>(of, dm_hi, px, py);
+            if (!orbit_ok) px[0] = NAN;
+            const float d0 = dm_lo + base_f;
+            for (int s = 0; s < ns; ++s)
+              zb[s * kWave + lane] = orbit_series_z<float, N>(px, py, of.ycs, fmaf(step_f, float(s0 + s), d0));
+          };
+          static_assert(kOrbitSeriesMin == 4 && kOrbitSeriesMax == 6, "one branch per order");
+          if (of.series == 4) series_chunk(std::integral_constant<int, 4>());
+          else if (of.series == 5) series_chunk(std::integral_constant<int, 5>());
+          else series_chunk(std::integral_constant<int, 6>());
           // the k-hat functions after the series, so that its coefficients
           // are not live across them
           if constexpr (MODEL == kModelMAKhat)

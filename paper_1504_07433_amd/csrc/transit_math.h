@@ -410,7 +410,7 @@ struct OrbitF {
   float sx, vx, y0, sy, vy, ycs;
   float cut_lo, cut_hi;   // in-transit window of dM (float, widened)
   int32_t circular, valid;
-  int32_t series;         // subsamples from the position series of their exposure
+  int32_t series;         // order of the per-exposure position series, 0: one solve per subsample
 };
 
 PT_HD OrbitF orbit_f(const OrbitConst& o) {
@@ -495,9 +495,10 @@ PT_HD float orbit_zf(const OrbitF& o, float dm) {
 //   x_j (1 - e cos E) = [j = 1] + e cos E_c A_j + e sin E_c B_j,
 // with E the eccentric anomaly at the centre; X' and Y are linear in S and
 // 1 - C.  One solve, one reciprocal and ~100 operations per exposure, then
-// 2 kOrbitSeries FMAs per subsample.
+// 2 N FMAs per subsample for order N; each light curve takes the lowest order
+// in kOrbitSeriesMin..kOrbitSeriesMax whose truncation bound (below) holds.
 // ---------------------------------------------------------------------------
-constexpr int kOrbitSeries = 6;
+constexpr int kOrbitSeriesMin = 4, kOrbitSeriesMax = 6;
 constexpr double kOrbitSeriesTol = 3e-8;      // truncation bound on z
 constexpr int kOrbitSeriesMinSubsamples = 4;  // below this one solve per subsample is cheaper
 
@@ -506,16 +507,16 @@ PT_HD double fma_t(double a, double b, double c) { return fma(a, b, c); }
 
 // Coefficients of X' and Y from sin x, 1 - cos x at the expansion point
 // (ec = e cos E_c, es = e sin E_c).
-template <class T>
+template <class T, int N>
 PT_HD void orbit_series_coef(T ec, T es, const OrbitFold<T>& f, T s, T v, T* px, T* py) {
   const T c0 = T(1) - v;
   const T q = Num<T>::rcp(T(1) - ec * c0 + es * s);
-  T mx[kOrbitSeries + 1], S[kOrbitSeries + 1], C[kOrbitSeries + 1];
+  T mx[N + 1], S[N + 1], C[N + 1];
   S[0] = s;
   C[0] = c0;
   mx[0] = T(0);
 #pragma unroll
-  for (int j = 1; j <= kOrbitSeries; ++j) {
+  for (int j = 1; j <= N; ++j) {
     T A = T(0), B = T(0);
 #pragma unroll
     for (int m = 1; m < j; ++m) {
@@ -533,12 +534,13 @@ PT_HD void orbit_series_coef(T ec, T es, const OrbitFold<T>& f, T s, T v, T* px,
   px[0] = f.sx * s + f.vx * v;
   py[0] = f.y0 + f.sy * s + f.vy * v;
 #pragma unroll
-  for (int j = 1; j <= kOrbitSeries; ++j) {
+  for (int j = 1; j <= N; ++j) {
     px[j] = f.sx * S[j] - f.vx * C[j];
     py[j] = f.sy * S[j] - f.vy * C[j];
   }
 }
 
+template <int N>
 PT_HD void orbit_series(const OrbitF& o, float dm, float* px, float* py) {
   float s, v;
   orbit_sv(o, dm, &s, &v);
@@ -549,15 +551,15 @@ PT_HD void orbit_series(const OrbitF& o, float dm, float* px, float* py) {
   f.sy = o.sy;
   f.vy = o.vy;
   f.ycs = o.ycs;
-  orbit_series_coef<float>(o.ec, o.es, f, s, v, px, py);
+  orbit_series_coef<float, N>(o.ec, o.es, f, s, v, px, py);
 }
 
 // Signed z at offset d from the expansion point.
-template <class T>
+template <class T, int N>
 PT_HD T orbit_series_z(const T* px, const T* py, T ycs, T d) {
-  T X = px[kOrbitSeries], Y = py[kOrbitSeries];
+  T X = px[N], Y = py[N];
 #pragma unroll
-  for (int j = kOrbitSeries - 1; j >= 0; --j) {
+  for (int j = N - 1; j >= 0; --j) {
     X = fma_t(X, d, px[j]);
     Y = fma_t(Y, d, py[j]);
   }
@@ -575,16 +577,22 @@ PT_HD T orbit_series_z(const T* px, const T* py, T ycs, T d) {
 // Y cos i a/R* - const below B = sqrt(2) a/R* (cosh t + 1), and each
 // remainder below B (dmax/r)^(N+1) / (1 - dmax/r); z's below sqrt(2) times
 // that.  The circle is named by t (0 < t < acosh(1/e)), which needs no
-// inversion of g.  Returns 1e300 when t is outside that range or r <= dmax.
-PT_HD double orbit_series_bound(const OrbitConst& o, double dmax, double t) {
+// inversion of g.  rem[N - kOrbitSeriesMin] receives the bound for each order
+// N; 1e300 when t is outside that range or r <= dmax.
+PT_HD void orbit_series_bounds(const OrbitConst& o, double dmax, double t, double* rem) {
+  for (int n = kOrbitSeriesMin; n <= kOrbitSeriesMax; ++n) rem[n - kOrbitSeriesMin] = 1e300;
   const double e = o.e;
-  if (!(e >= 0.0 && e < 1.0) || !(t > 0.0)) return 1e300;
-  if (e > 0.0 && !(t < ::acosh(1.0 / e))) return 1e300;
+  if (!(e >= 0.0 && e < 1.0) || !(t > 0.0)) return;
+  if (e > 0.0 && !(t < ::acosh(1.0 / e))) return;
   const double r = t - e * ::sinh(t);
-  if (!(r > dmax)) return 1e300;
+  if (!(r > dmax)) return;
   const double B = 1.4142135623730951 * o.aR * (::cosh(t) + 1.0);
   const double x = dmax / r;
-  return 1.4142135623730951 * B * ::pow(x, double(kOrbitSeries + 1)) / (1.0 - x);
+  double c = 1.4142135623730951 * B * ::pow(x, double(kOrbitSeriesMin + 1)) / (1.0 - x);
+  for (int n = kOrbitSeriesMin; n <= kOrbitSeriesMax; ++n) {
+    rem[n - kOrbitSeriesMin] = c;
+    c *= x;
+  }
 }
 
 // ---------------------------------------------------------------------------
