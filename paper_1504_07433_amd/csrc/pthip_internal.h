@@ -81,7 +81,10 @@ struct BatchArgs {
   OrbitConst* oc;       // [n_lc], written by the window kernel
   OrbitF* ocf;          // [n_lc] float form, written by the window kernel
   BandConst* bc;        // [n_band], written by the prep kernel
-  void* gtab;           // Gimenez per-band tables [n_band][nldc+1][npol] (float or double)
+  void* gtab;           // Gimenez per-band rows [n_band][nldc+1][gim_row(npol)]: double Jacobi
+                        // coefficients (FP64) or float Chebyshev coefficients (float path)
+  double* gtab64;       // float path: the double Jacobi rows the Chebyshev rows come from
+  const double* gconn;  // [nldc+1][row][row] Chebyshev coefficients of P_j^(0,nu+1)
   const void* grec;     // shared recurrence coefficients [(nldc+1)][npol][3]
   const double4* gbcoef;  // [(nldc+1)][npol] {A_j, B_j, C_j, A'_{n,j}} of the band tables
   unsigned int* queue;  // kQueues counters, kQueueStride apart (reset by the prep kernel)
@@ -129,6 +132,8 @@ hipError_t launch_orbit_z(const double* t, int64_t n, const OrbitConst& o, int p
                           hipStream_t s);
 hipError_t launch_ma_quad(const double* z, int64_t n, double k, const double* u, int nb, int prec,
                           double* flux, hipStream_t s);
+hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, int nldc, int npol, float* cheb,
+                           hipStream_t s);
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
                              const double4* bcoef, void* tab, int prec, hipStream_t s);
 hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u, int nldc, int nb,

@@ -3,6 +3,7 @@
 // k_orbit_z          z(t) for one orbit                       (Sect. 1)
 // k_ma_quad          quadratic Mandel-Agol, one k, nb bands     (Sect. 2.2)
 // k_gim_band_tables  Gimenez per-band tables b^2 A' P^2         (Sect. 2.1.4)
+// k_gim_cheb         their Chebyshev rows for the float path
 // k_gimenez          Gimenez, one k, nb bands                   (Sect. 2.1)
 // k_batch_prep       per-band constants, queue reset
 // k_lc_window        per-light-curve orbit constants and in-transit window
@@ -165,6 +166,62 @@ __global__ __launch_bounds__(256) void k_gim_band_tables(const double* __restric
       wave_lds_sync();
     }
   }
+}
+
+// Chebyshev rows of the float path: row (band, n) of the double band table
+// times M_n, cheb[band][n][i] = sum_j tab64[band][n][j] M_n[j][i] (M_n[j][i] = 0
+// for i > j and beyond npol).  A wavefront takes kChebBands bands of one n,
+// lanes over i: each M_n value it loads serves all of them, and the table
+// rows are read by scalar loads.
+constexpr int kChebBands = 8;
+
+__global__ __launch_bounds__(256) void k_gim_cheb(const double* __restrict__ tab64, const double* __restrict__ conn,
+                                                  int n_band, int nldc, int npol, float* __restrict__ cheb) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = gim_row(npol), nr = nldc + 1;
+  const int64_t groups = (int64_t)((n_band + kChebBands - 1) / kChebBands) * nr;
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  // the wave's index, made wave-uniform so that the table rows are read by scalar loads
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; g < groups; g += n_waves) {
+    const int n = (int)(g % nr);
+    const int64_t b0 = (g / nr) * kChebBands;
+    const int nb = n_band - b0 < kChebBands ? (int)(n_band - b0) : kChebBands;
+    const PT_CONST_AS double* t[kChebBands];
+#pragma unroll
+    for (int q = 0; q < kChebBands; ++q)   // bands past the end re-read the first one
+      t[q] = (const PT_CONST_AS double*)(tab64 + ((b0 + (q < nb ? q : 0)) * nr + n) * row);
+    const double* __restrict__ M = conn + (int64_t)n * row * row;
+    for (int i0 = 0; i0 < row; i0 += kWave) {
+      const int i = i0 + lane;
+      if (i >= row) break;
+      double acc[kChebBands];
+#pragma unroll
+      for (int q = 0; q < kChebBands; ++q) acc[q] = 0.0;
+      // four terms per step (the table rows are padded to a multiple of four)
+      for (int jj = i0; jj < npol; jj += 4) {
+        double m[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m[u] = M[(int64_t)(jj + u) * row + i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < kChebBands; ++q) acc[q] = fma(t[q][jj + u], m[u], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < kChebBands; ++q)
+        if (q < nb) cheb[((b0 + q) * nr + n) * row + i] = float(acc[q]);
+    }
+  }
+}
+
+hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, int nldc, int npol, float* cheb,
+                           hipStream_t s) {
+  const int64_t groups = (int64_t)((n_band + kChebBands - 1) / kChebBands) * (nldc + 1);
+  if (groups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gim_cheb, dim3(grid_for(groups * kWave, 256)), dim3(256), 0, s, tab64, conn, n_band, nldc,
+                     npol, cheb);
+  return hipGetLastError();
 }
 
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
@@ -409,7 +466,11 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
 #pragma unroll
   for (int m = 0; m < 5; ++m) {             // static band-weight indices (nldc <= 4)
     if (m > nldc) break;
-    loss += band_w<T>(bc, m) * gimenez_power(om, m) * gimenez_clenshaw(tab + m * row, rec + 4 * m * row, npol, x);
+    // float: Chebyshev rows; double: Jacobi rows and their recurrence
+    T sum;
+    if constexpr (sizeof(T) == 4) sum = gimenez_cheb_clenshaw(tab + m * row, npol, x);
+    else sum = gimenez_clenshaw(tab + m * row, rec + 4 * m * row, npol, x);
+    loss += band_w<T>(bc, m) * gimenez_power(om, m) * sum;
   }
   return loss;
 }
@@ -892,7 +953,14 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
-    err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab, prec, s);
+    if (prec == kPrecFP64) {
+      err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab, kPrecFP64, s);
+    } else {
+      // band tables in double, then their Chebyshev rows in float
+      err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab64, kPrecFP64, s);
+      if (err == hipSuccess)
+        err = launch_gim_cheb(a.gtab64, a.gconn, a.n_band, a.nldc, a.npol, (float*)a.gtab, s);
+    }
     if (err != hipSuccess) return err;
   }
   if (model == kModelMAInterp && a.ltab) {

@@ -107,7 +107,7 @@ struct DevBuf {
 // terms {A_j, B_j, C_j, A'_{n,j}} (double) and the Clenshaw recurrence
 // coefficients {A_j, B_j, C_{j+1}, 0} in float and double.
 struct GimTables {
-  DevBuf bcoef, rec32, rec64;
+  DevBuf bcoef, rec32, rec64, conn;
 };
 static std::map<std::tuple<int, int, int>, std::unique_ptr<GimTables>> g_gim;
 
@@ -136,7 +136,13 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
       r64[o] = A; r64[o + 1] = B; r64[o + 2] = Cn;
       r32[o] = float(A); r32[o + 1] = float(B); r32[o + 2] = float(Cn);
     }
+  // Chebyshev coefficients of P_j^(0,nu+1), j < npol, for the float path's rows
+  const size_t nc = (size_t)row * row;
+  std::vector<double> conn((size_t)(nldc + 1) * nc);
+  for (int n = 0; n <= nldc; ++n) gimenez_cheb_conn(n, npol, conn.data() + n * nc);
   auto t = std::make_unique<GimTables>();
+  PT_HIP(t->conn.ensure(conn.size() * sizeof(double)));
+  PT_HIP(hipMemcpy(t->conn.p, conn.data(), conn.size() * sizeof(double), hipMemcpyHostToDevice));
   PT_HIP(t->bcoef.ensure(nn * sizeof(double4)));
   PT_HIP(t->rec64.ensure(nr * sizeof(double)));
   PT_HIP(t->rec32.ensure(nr * sizeof(float)));
@@ -186,7 +192,8 @@ struct Plan {
   int32_t n_lc = 0, n_band = 0, nldc = 0, npol = 0, model = 0, prec = 0;
   std::vector<int64_t> t_count;
   std::vector<int32_t> nss, band_off;
-  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, queue, khat, ztab, ltab;
+  DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, gtab64, queue, khat, ztab,
+      ltab;
   std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
   LaunchShape shape;
   bool tuned = false;
@@ -398,7 +405,9 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
     const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
-    PT_HIP(p->gtab.ensure(std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * gim_row(npol) * es));
+    const size_t terms = std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * gim_row(npol);
+    PT_HIP(p->gtab.ensure(terms * es));
+    if (prec != PT_PREC_FP64) PT_HIP(p->gtab64.ensure(terms * sizeof(double)));
   }
   auto tu = g_tuned.find(key);
   if (tu != g_tuned.end()) {
@@ -480,6 +489,8 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     st = gim_tables(p->nldc, p->npol, &g);
     if (st != PT_OK) return st;
     a->gtab = p->gtab.p;
+    a->gtab64 = (double*)p->gtab64.p;
+    a->gconn = (const double*)g->conn.p;
     a->grec = p->prec == PT_PREC_FP64 ? g->rec64.p : g->rec32.p;
     a->gbcoef = (const double4*)g->bcoef.p;
   }
@@ -603,12 +614,16 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
     if (st != PT_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
+  // the double Jacobi row of each n; the float path evaluates their Chebyshev rows
   void* tab = nullptr;
-  const size_t bytes = (size_t)(nldc + 1) * gim_row(npol) * (pr == kPrecFP64 ? 8 : 4);
-  PT_HIP(hipMallocAsync(&tab, bytes, s));
-  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double4*)g->bcoef.p, tab, pr, s);
+  const size_t terms = (size_t)(nldc + 1) * gim_row(npol);
+  PT_HIP(hipMallocAsync(&tab, terms * (8 + (pr == kPrecFP64 ? 0 : 4)), s));
+  float* cheb = (float*)((char*)tab + terms * 8);
+  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double4*)g->bcoef.p, tab, kPrecFP64, s);
+  if (e1 == hipSuccess && pr != kPrecFP64)
+    e1 = launch_gim_cheb((const double*)tab, (const double*)g->conn.p, 1, nldc, npol, cheb, s);
   hipError_t e2 = e1 == hipSuccess
-                      ? launch_gimenez(z, n, k, u, nldc, nb, npol, tab,
+                      ? launch_gimenez(z, n, k, u, nldc, nb, npol, pr == kPrecFP64 ? tab : (void*)cheb,
                                        pr == kPrecFP64 ? g->rec64.p : g->rec32.p, pr, flux, s)
                       : e1;
   hipFreeAsync(tab, s);

@@ -852,6 +852,61 @@ PT_HD void gimenez_rec_coef(int n, int j, double* A, double* B, double* Cn) {
   jacobi_coef(j + 1, 0.0, be, &A1, &B1, Cn);
 }
 
+// Chebyshev form of the same sums for the float path.  With x T_0 = T_1 and
+// x T_i = (T_{i+1} + T_{i-1}) / 2, the recurrence above gives the Chebyshev
+// coefficients of every P_j^(0,nu+1) (row j of M_n: M[j * gim_row(npol) + i],
+// i <= j), so a band's sum_j t_j P_j(x) is sum_i (sum_j t_j M[j][i]) T_i(x),
+// evaluated by Clenshaw's recurrence for Chebyshev series with two operations
+// per term instead of four.  The conversion runs in double; in float the
+// Chebyshev sum is as accurate as the Jacobi one (host-measured for npol up
+// to 512), since Chebyshev coefficients are bounded by the sum's maximum.
+PT_HD void gimenez_cheb_conn(int n, int npol, double* M) {
+  const int row = gim_row(npol);
+  for (int i = 0; i < row * row; ++i) M[i] = 0.0;
+  const double be = 0.5 * (n + 2) + 1.0;
+  M[0] = 1.0;                                       // P_0 = T_0
+  for (int j = 0; j + 1 < npol; ++j) {
+    double A, B, C;
+    jacobi_coef(j, 0.0, be, &A, &B, &C);
+    const double* p = M + (size_t)j * row;
+    const double* pm1 = j > 0 ? M + (size_t)(j - 1) * row : nullptr;
+    double* pn = M + (size_t)(j + 1) * row;
+    for (int i = 0; i <= j + 1; ++i) {
+      // (x p)_i = p_{i-1} (i = 1: p_0 whole, i > 1: half) + p_{i+1} / 2
+      double xp = 0.0;
+      if (i == 1) xp += p[0];
+      else if (i > 1) xp += 0.5 * p[i - 1];
+      if (i + 1 <= j) xp += 0.5 * p[i + 1];
+      pn[i] = A * xp + B * (i <= j ? p[i] : 0.0) - C * (pm1 && i < j ? pm1[i] : 0.0);
+    }
+  }
+}
+
+// sum_i c_i T_i(x) by Clenshaw's recurrence b_i = c_i + 2x b_{i+1} - b_{i+2},
+// sum = c_0 + x b_1 - b_2; cn: one padded row, read four terms per step.
+template <class T>
+PT_HD T gimenez_cheb_clenshaw(const T* cn_, int npol, T x) {
+  const int row = gim_row(npol);
+  const PT_CONST_AS T* cp = (const PT_CONST_AS T*)cn_ + (row - 4);
+  const T x2 = x + x;
+  T b1 = T(0), b2 = T(0);
+  for (int blk = row / 4; blk > 1; --blk, cp -= 4) {
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      const T b0 = x2 * b1 + (cp[i] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+  }
+#pragma unroll
+  for (int i = 3; i >= 1; --i) {
+    const T b0 = x2 * b1 + (cp[i] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return x * b1 + (cp[0] - b2);
+}
+
 // (1 - c^2)^(nu+1) for nu = (n+2)/2
 template <class T>
 PT_HD T gimenez_power(T om, int n) {
@@ -886,8 +941,9 @@ PT_HD T gimenez_clenshaw(const T* tn_, const T* rn_, int npol, T x) {
 
 // alpha_n = (1-c^2)^(nu+1) sum_{j<npol} T[n][j] P_j^(0,nu+1)(1-2c^2) by
 // Clenshaw's backward recurrence; tab rows T[n][.] and rec rows
-// {A_j, B_j, C_{j+1}, 0}[n][.] are padded to gim_row(npol) terms.  Returns 0
-// for c >= 1 (no overlap).
+// {A_j, B_j, C_{j+1}, 0}[n][.] are padded to gim_row(npol) terms (in float,
+// tab rows are the Chebyshev coefficients of the same sums).  Returns 0 for
+// c >= 1 (no overlap).
 template <class T>
 PT_HD void gimenez_alpha(T z, T inv1pk, int nldc, int npol, const T* tab, const T* rec, T* alpha) {
   const T c = z * inv1pk;
@@ -896,7 +952,10 @@ PT_HD void gimenez_alpha(T z, T inv1pk, int nldc, int npol, const T* tab, const 
   const int row = gim_row(npol);
   for (int n = 0; n <= nldc; ++n) {
     if (!(om > T(0))) { alpha[n] = (om == om) ? T(0) : om; continue; }
-    alpha[n] = gimenez_power(om, n) * gimenez_clenshaw(tab + n * row, rec + 4 * n * row, npol, x);
+    // float: tab holds Chebyshev rows (rec unused); double: Jacobi rows
+    const T sum = sizeof(T) == 4 ? gimenez_cheb_clenshaw(tab + n * row, npol, x)
+                                 : gimenez_clenshaw(tab + n * row, rec + 4 * n * row, npol, x);
+    alpha[n] = gimenez_power(om, n) * sum;
   }
 }
 
