@@ -3,7 +3,8 @@
 // k_orbit_z          z(t) for one orbit                       (Sect. 1)
 // k_ma_quad          quadratic Mandel-Agol, one k, nb bands     (Sect. 2.2)
 // k_gim_band_tables  Gimenez per-band tables b^2 A' P^2         (Sect. 2.1.4)
-// k_gim_cheb         their Chebyshev rows for the float path
+// k_gim_cheb         their Chebyshev rows for the float path (pt_gimenez)
+// k_gim_cheb_fold    per band, the float batch path's two folded rows
 // k_gimenez          Gimenez, one k, nb bands                   (Sect. 2.1)
 // k_batch_prep       per-band constants, queue reset
 // k_lc_window        per-light-curve orbit constants and in-transit window
@@ -221,6 +222,81 @@ hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, 
   if (groups == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gim_cheb, dim3(grid_for(groups * kWave, 256)), dim3(256), 0, s, tab64, conn, n_band, nldc,
                      npol, cheb);
+  return hipGetLastError();
+}
+
+// Folded rows of the float batch path: per band E[i] and O[i] (gim_fold_row
+// coefficients each) with E = sum_{n even} w_n C'_n, O = sum_{n odd} w_n C'_n,
+// C'_n[i] = sum_j T_n[j] M'_n[j][i], M'_n the Chebyshev rows of
+// ((1+x)/2)^q_n P_j^(0,nu+1) and w_n the band's weights; the band's loss is then
+// E(x) + sqrt(1 - c^2) O(x).  A wavefront takes kFoldBands bands, lanes over i
+// (fewer than k_gim_cheb: each wave runs all n, so more waves keep the loads
+// in flight).
+constexpr int kFoldBands = 4;
+__global__ __launch_bounds__(256) void k_gim_cheb_fold(const double* __restrict__ tab64,
+                                                       const double* __restrict__ connq,
+                                                       const BandConst* __restrict__ bc, int n_band, int nldc,
+                                                       int npol, float* __restrict__ fold) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = gim_row(npol), row2 = gim_fold_row(npol), nr = nldc + 1;
+  const int64_t groups = (n_band + kFoldBands - 1) / kFoldBands;
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; g < groups; g += n_waves) {
+    const int64_t b0 = g * kFoldBands;
+    const int nb = n_band - b0 < kFoldBands ? (int)(n_band - b0) : kFoldBands;
+    for (int i0 = 0; i0 < row2; i0 += kWave) {
+      const int i = i0 + lane;
+      if (i >= row2) break;
+      // rows j < i - kGimFoldPow hold no term of degree i
+      const int j0 = (i0 > kGimFoldPow ? i0 - kGimFoldPow : 0) & ~3;
+      double e[kFoldBands], o[kFoldBands];
+#pragma unroll
+      for (int q = 0; q < kFoldBands; ++q) e[q] = o[q] = 0.0;
+      for (int n = 0; n < nr; ++n) {
+        const PT_CONST_AS double* t[kFoldBands];
+#pragma unroll
+        for (int q = 0; q < kFoldBands; ++q)   // bands past the end re-read the first one
+          t[q] = (const PT_CONST_AS double*)(tab64 + ((b0 + (q < nb ? q : 0)) * nr + n) * row);
+        const double* __restrict__ M = connq + (int64_t)n * row * row2;
+        double c[kFoldBands];
+#pragma unroll
+        for (int q = 0; q < kFoldBands; ++q) c[q] = 0.0;
+        for (int jj = j0; jj < npol; jj += 4) {
+          double m[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) m[u] = M[(int64_t)(jj + u) * row2 + i];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < kFoldBands; ++q) c[q] = fma(t[q][jj + u], m[u], c[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kFoldBands; ++q) {
+          // the band's weight w_n by one scalar load
+          const PT_CONST_AS double* wq = (const PT_CONST_AS double*)bc[b0 + (q < nb ? q : 0)].wd;
+          const double w = wq[n];
+          if (n & 1) o[q] = fma(w, c[q], o[q]);
+          else e[q] = fma(w, c[q], e[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kFoldBands; ++q) {
+        if (q < nb) {
+          fold[(b0 + q) * 2 * row2 + i] = float(e[q]);
+          fold[(b0 + q) * 2 * row2 + row2 + i] = float(o[q]);
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_gim_cheb_fold(const double* tab64, const double* connq, const BandConst* bc, int n_band, int nldc,
+                                int npol, float* fold, hipStream_t s) {
+  const int64_t groups = (n_band + kFoldBands - 1) / kFoldBands;
+  if (groups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gim_cheb_fold, dim3(grid_for(groups * kWave, 256)), dim3(256), 0, s, tab64, connq, bc, n_band,
+                     nldc, npol, fold);
   return hipGetLastError();
 }
 
@@ -461,16 +537,18 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
   const T om = T(1) - c * c;
   if (om <= T(0)) return T(0);
   const T x = T(1) - T(2) * c * c;
+  if constexpr (sizeof(T) == 4) {
+    // float: the band's folded rows E, O (weights and powers of 1 - c^2 inside)
+    const int n2 = npol + kGimFoldPow;
+    return gimenez_cheb_clenshaw(tab, n2, x) + Num<float>::sqrt(om) * gimenez_cheb_clenshaw(tab + gim_row(n2), n2, x);
+  }
+  // double: Jacobi rows and their recurrence, one sum per n
   const int row = gim_row(npol);
   T loss = T(0);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {             // static band-weight indices (nldc <= 4)
     if (m > nldc) break;
-    // float: Chebyshev rows; double: Jacobi rows and their recurrence
-    T sum;
-    if constexpr (sizeof(T) == 4) sum = gimenez_cheb_clenshaw(tab + m * row, npol, x);
-    else sum = gimenez_clenshaw(tab + m * row, rec + 4 * m * row, npol, x);
-    loss += band_w<T>(bc, m) * gimenez_power(om, m) * sum;
+    loss += band_w<T>(bc, m) * gimenez_power(om, m) * gimenez_clenshaw(tab + m * row, rec + 4 * m * row, npol, x);
   }
   return loss;
 }
@@ -556,7 +634,7 @@ hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab
 __global__ __launch_bounds__(256) void k_gim_ztable(BatchArgs a) {
   const int nodes = a.zin + a.zlimb;
   const int64_t total = (int64_t)a.n_band * nodes, stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t tab_stride = (int64_t)(a.nldc + 1) * gim_row(a.npol);
+  const int64_t tab_stride = gim_band_stride(false, a.nldc, a.npol);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int bnd = (int)(e / nodes), j = (int)(e % nodes);
     const BandConst* bc = a.bc + bnd;
@@ -690,7 +768,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
   const T* __restrict__ grec = reinterpret_cast<const T*>(a.grec);
   T* __restrict__ flux = reinterpret_cast<T*>(a.flux);
   const T* __restrict__ obs = reinterpret_cast<const T*>(a.obs);
-  const int64_t tab_stride = (int64_t)(a.nldc + 1) * gim_row(a.npol);
+  const int64_t tab_stride = gim_band_stride(PREC == kPrecFP64, a.nldc, a.npol);
 
   // Start on the sub-queue of this workgroup's slot (workgroups are handed to
   // the XCDs in turn), move to the next one when it runs dry, stop when all
@@ -956,10 +1034,10 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
     if (prec == kPrecFP64) {
       err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab, kPrecFP64, s);
     } else {
-      // band tables in double, then their Chebyshev rows in float
+      // band tables in double, then each band's two folded Chebyshev rows in float
       err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab64, kPrecFP64, s);
       if (err == hipSuccess)
-        err = launch_gim_cheb(a.gtab64, a.gconn, a.n_band, a.nldc, a.npol, (float*)a.gtab, s);
+        err = launch_gim_cheb_fold(a.gtab64, a.gconnq, a.bc, a.n_band, a.nldc, a.npol, (float*)a.gtab, s);
     }
     if (err != hipSuccess) return err;
   }

@@ -107,7 +107,7 @@ struct DevBuf {
 // terms {A_j, B_j, C_j, A'_{n,j}} (double) and the Clenshaw recurrence
 // coefficients {A_j, B_j, C_{j+1}, 0} in float and double.
 struct GimTables {
-  DevBuf bcoef, rec32, rec64, conn;
+  DevBuf bcoef, rec32, rec64, conn, connq;
 };
 static std::map<std::tuple<int, int, int>, std::unique_ptr<GimTables>> g_gim;
 
@@ -140,9 +140,16 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
   const size_t nc = (size_t)row * row;
   std::vector<double> conn((size_t)(nldc + 1) * nc);
   for (int n = 0; n <= nldc; ++n) gimenez_cheb_conn(n, npol, conn.data() + n * nc);
+  // the same rows times ((1+x)/2)^q_n, for the batch's folded rows
+  const int row2 = gim_fold_row(npol);
+  const size_t nq = (size_t)row * row2;
+  std::vector<double> connq((size_t)(nldc + 1) * nq);
+  for (int n = 0; n <= nldc; ++n) gimenez_cheb_conn_q(n, npol, row2, gim_fold_q(n), connq.data() + n * nq);
   auto t = std::make_unique<GimTables>();
   PT_HIP(t->conn.ensure(conn.size() * sizeof(double)));
   PT_HIP(hipMemcpy(t->conn.p, conn.data(), conn.size() * sizeof(double), hipMemcpyHostToDevice));
+  PT_HIP(t->connq.ensure(connq.size() * sizeof(double)));
+  PT_HIP(hipMemcpy(t->connq.p, connq.data(), connq.size() * sizeof(double), hipMemcpyHostToDevice));
   PT_HIP(t->bcoef.ensure(nn * sizeof(double4)));
   PT_HIP(t->rec64.ensure(nr * sizeof(double)));
   PT_HIP(t->rec32.ensure(nr * sizeof(float)));
@@ -404,10 +411,14 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   PT_HIP(hipMemset(p->queue.p, 0, kQueues * kQueueStride * sizeof(unsigned int)));
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
-    const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
-    const size_t terms = std::max<size_t>(1, (size_t)p->n_band) * (b->nldc + 1) * gim_row(npol);
-    PT_HIP(p->gtab.ensure(terms * es));
-    if (prec != PT_PREC_FP64) PT_HIP(p->gtab64.ensure(terms * sizeof(double)));
+    const size_t nb = std::max<size_t>(1, (size_t)p->n_band);
+    const size_t terms = nb * (b->nldc + 1) * gim_row(npol);       // Jacobi rows, double
+    if (prec == PT_PREC_FP64) {
+      PT_HIP(p->gtab.ensure(terms * sizeof(double)));
+    } else {
+      PT_HIP(p->gtab64.ensure(terms * sizeof(double)));
+      PT_HIP(p->gtab.ensure(nb * (size_t)gim_band_stride(false, b->nldc, npol) * sizeof(float)));
+    }
   }
   auto tu = g_tuned.find(key);
   if (tu != g_tuned.end()) {
@@ -491,6 +502,7 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     a->gtab = p->gtab.p;
     a->gtab64 = (double*)p->gtab64.p;
     a->gconn = (const double*)g->conn.p;
+    a->gconnq = (const double*)g->connq.p;
     a->grec = p->prec == PT_PREC_FP64 ? g->rec64.p : g->rec32.p;
     a->gbcoef = (const double4*)g->bcoef.p;
   }

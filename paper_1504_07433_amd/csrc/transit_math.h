@@ -860,9 +860,16 @@ PT_HD void gimenez_rec_coef(int n, int j, double* A, double* B, double* Cn) {
 // per term instead of four.  The conversion runs in double; in float the
 // Chebyshev sum is as accurate as the Jacobi one (host-measured for npol up
 // to 512), since Chebyshev coefficients are bounded by the sum's maximum.
-PT_HD void gimenez_cheb_conn(int n, int npol, double* M) {
-  const int row = gim_row(npol);
-  for (int i = 0; i < row * row; ++i) M[i] = 0.0;
+// gimenez_cheb_conn_q also multiplies each row by ((1 + x)/2)^q, i.e. by
+// (1 - c^2)^q: with x = 1 - 2c^2 the factor (1 - c^2)^(nu+1) of alpha_n is a
+// polynomial in x for even n and sqrt(1 - c^2) times one for odd n, so a
+// band's whole loss sum_n w_n alpha_n becomes E(x) + sqrt(1 - c^2) O(x) with
+// two Chebyshev series (its limb-darkening weights folded in).
+constexpr int kGimFoldPow = 4;                  // largest integer power, n = 4
+PT_HD constexpr int gim_fold_row(int npol) { return gim_row(npol + kGimFoldPow); }
+PT_HD constexpr int gim_fold_q(int n) { return 2 + n / 2; }
+PT_HD void gimenez_cheb_conn_q(int n, int npol, int row, int q, double* M) {
+  for (int i = 0; i < npol * row; ++i) M[i] = 0.0;
   const double be = 0.5 * (n + 2) + 1.0;
   M[0] = 1.0;                                       // P_0 = T_0
   for (int j = 0; j + 1 < npol; ++j) {
@@ -880,6 +887,28 @@ PT_HD void gimenez_cheb_conn(int n, int npol, double* M) {
       pn[i] = A * xp + B * (i <= j ? p[i] : 0.0) - C * (pm1 && i < j ? pm1[i] : 0.0);
     }
   }
+  // times ((1 + x)/2)^q: p <- (p + x p) / 2, q times per row (the degree grows
+  // by one each time; row >= npol + q)
+  for (int j = 0; j < npol; ++j) {
+    double* p = M + (size_t)j * row;
+    for (int r = 0; r < q; ++r) {
+      const int deg = j + r;                        // current degree of row j
+      double prev = 0.0;                            // p[i-1] before its update
+      for (int i = 0; i <= deg + 1; ++i) {
+        double xp = 0.0;
+        if (i == 1) xp += prev;
+        else if (i > 1) xp += 0.5 * prev;
+        if (i + 1 <= deg) xp += 0.5 * p[i + 1];
+        const double cur = i <= deg ? p[i] : 0.0;
+        p[i] = 0.5 * (cur + xp);
+        prev = cur;
+      }
+    }
+  }
+}
+
+PT_HD void gimenez_cheb_conn(int n, int npol, double* M) {
+  gimenez_cheb_conn_q(n, npol, gim_row(npol), 0, M);
 }
 
 // sum_i c_i T_i(x) by Clenshaw's recurrence b_i = c_i + 2x b_{i+1} - b_{i+2},

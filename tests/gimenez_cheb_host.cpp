@@ -33,3 +33,32 @@ extern "C" int gim_cheb_alpha64(const double* z, int nz, double k, int nldc, int
   }
   return 0;
 }
+
+// The batch's folded form: sum_n w_n alpha_n at each z as E(x) + sqrt(1 - c^2)
+// O(x), E and O the weighted sums of the rows times ((1+x)/2)^q_n.
+extern "C" int gim_fold_loss64(const double* z, int nz, double k, int nldc, int npol, const double* w,
+                               double* loss) {
+  if (nldc < 0 || nldc > 4 || npol < 1 || npol > 512) return 1;
+  const int row = pt::gim_row(npol), row2 = pt::gim_fold_row(npol);
+  std::vector<double> ap((size_t)(nldc + 1) * npol), tab((size_t)(nldc + 1) * row);
+  std::vector<double> M((size_t)row * row2), E(row2, 0.0), O(row2, 0.0);
+  for (int n = 0; n <= nldc; ++n)
+    for (int j = 0; j < npol; ++j) ap[(size_t)n * npol + j] = pt::gimenez_aprime(n, j);
+  pt::gimenez_band_table<double>(k, nldc, npol, ap.data(), tab.data());
+  for (int n = 0; n <= nldc; ++n) {
+    pt::gimenez_cheb_conn_q(n, npol, row2, pt::gim_fold_q(n), M.data());
+    for (int i = 0; i < row2; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < npol; ++j) acc += tab[(size_t)n * row + j] * M[(size_t)j * row2 + i];
+      (n & 1 ? O : E)[i] += w[n] * acc;
+    }
+  }
+  const int n2 = npol + pt::kGimFoldPow;
+  for (int q = 0; q < nz; ++q) {
+    const double c = z[q] / (1.0 + k), om = 1.0 - c * c, x = 1.0 - 2.0 * c * c;
+    loss[q] = om > 0.0 ? pt::gimenez_cheb_clenshaw<double>(E.data(), n2, x) +
+                             sqrt(om) * pt::gimenez_cheb_clenshaw<double>(O.data(), n2, x)
+                       : 0.0;
+  }
+  return 0;
+}

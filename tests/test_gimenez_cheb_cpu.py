@@ -22,6 +22,8 @@ def lib(tmp_path_factory):
     dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
     L.gim_cheb_alpha64.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp]
     L.gim_cheb_alpha64.restype = ctypes.c_int
+    L.gim_fold_loss64.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
+    L.gim_fold_loss64.restype = ctypes.c_int
     return L
 
 
@@ -35,3 +37,19 @@ def test_chebyshev_form_matches_oracle(lib, oracle, npol):
         ref = np.array([oracle.gimenez_alpha(zz, k, nldc, npol) for zz in z])
         scale = np.abs(ref).max()
         assert np.abs(got - ref).max() <= 1e-11 * max(scale, 1e-3), (npol, k, np.abs(got - ref).max(), scale)
+
+
+@pytest.mark.parametrize("npol,nldc", [(1, 1), (5, 2), (20, 4), (50, 2), (50, 3), (200, 4)])
+def test_folded_form_matches_oracle(lib, oracle, npol, nldc):
+    """The batch's float path folds a band's limb-darkening weights and the
+    factors (1 - c^2)^(nu+1) into two Chebyshev series E, O: the band's loss
+    sum_n w_n alpha_n = E(x) + sqrt(1 - c^2) O(x)."""
+    rng = np.random.default_rng(npol + nldc)
+    for k in (0.03, 0.1, 0.3, 0.7):
+        w = np.ascontiguousarray(rng.uniform(-1, 1, nldc + 1))
+        z = np.ascontiguousarray(np.linspace(0.0, 1.0 + k, 157)[:-1])
+        got = np.zeros(len(z))
+        assert lib.gim_fold_loss64(z, len(z), k, nldc, npol, w, got) == 0
+        ref = np.array([np.dot(w, oracle.gimenez_alpha(zz, k, nldc, npol)) for zz in z])
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-11 * max(scale, 1e-3), (npol, nldc, k, np.abs(got - ref).max(), scale)
