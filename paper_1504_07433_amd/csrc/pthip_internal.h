@@ -81,12 +81,11 @@ struct BatchArgs {
   OrbitConst* oc;       // [n_lc], written by the window kernel
   OrbitF* ocf;          // [n_lc] float form, written by the window kernel
   BandConst* bc;        // [n_band], written by the prep kernel
-  void* gtab;           // Gimenez per-band rows: FP64 [n_band][nldc+1][gim_row(npol)] double Jacobi
-                        // coefficients; float [n_band][2][gim_fold_row(npol)] folded Chebyshev rows
-  double* gtab64;       // float path: the double Jacobi rows the Chebyshev rows come from
+  void* gtab;           // Gimenez per-band folded Chebyshev rows [n_band][2][gim_fold_row(npol)]
+                        // in the working type
+  double* gtab64;       // the double Jacobi rows [n_band][nldc+1][gim_row(npol)] they come from
   const double* gconn;  // [nldc+1][row][row] Chebyshev coefficients of P_j^(0,nu+1)
   const double* gconnq; // [nldc+1][row][gim_fold_row] the same times ((1+x)/2)^q_n
-  const void* grec;     // shared recurrence coefficients [(nldc+1)][npol][3]
   const double4* gbcoef;  // [(nldc+1)][npol] {A_j, B_j, C_j, A'_{n,j}} of the band tables
   unsigned int* queue;  // kQueues counters, kQueueStride apart (reset by the prep kernel)
   void* flux;
@@ -133,13 +132,10 @@ hipError_t launch_orbit_z(const double* t, int64_t n, const OrbitConst& o, int p
                           hipStream_t s);
 hipError_t launch_ma_quad(const double* z, int64_t n, double k, const double* u, int nb, int prec,
                           double* flux, hipStream_t s);
-// Per-band stride of the batch's Gimenez rows (FP64: Jacobi rows per n; float:
-// the two folded Chebyshev rows).
-PT_HD int64_t gim_band_stride(bool fp64, int nldc, int npol) {
-  return fp64 ? (int64_t)(nldc + 1) * gim_row(npol) : 2 * (int64_t)gim_fold_row(npol);
-}
+// Per-band stride of the batch's Gimenez rows (the two folded Chebyshev rows).
+PT_HD int64_t gim_band_stride(int npol) { return 2 * (int64_t)gim_fold_row(npol); }
 hipError_t launch_gim_cheb_fold(const double* tab64, const double* connq, const BandConst* bc, int n_band, int nldc,
-                                int npol, float* fold, hipStream_t s);
+                                int npol, void* fold, int prec, hipStream_t s);
 hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, int nldc, int npol, float* cheb,
                            hipStream_t s);
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,

@@ -225,7 +225,7 @@ hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, 
   return hipGetLastError();
 }
 
-// Folded rows of the float batch path: per band E[i] and O[i] (gim_fold_row
+// Folded rows of the batch path: per band E[i] and O[i] (gim_fold_row
 // coefficients each) with E = sum_{n even} w_n C'_n, O = sum_{n odd} w_n C'_n,
 // C'_n[i] = sum_j T_n[j] M'_n[j][i], M'_n the Chebyshev rows of
 // ((1+x)/2)^q_n P_j^(0,nu+1) and w_n the band's weights; the band's loss is then
@@ -233,10 +233,11 @@ hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, 
 // (fewer than k_gim_cheb: each wave runs all n, so more waves keep the loads
 // in flight).
 constexpr int kFoldBands = 4;
+template <class T>
 __global__ __launch_bounds__(256) void k_gim_cheb_fold(const double* __restrict__ tab64,
                                                        const double* __restrict__ connq,
                                                        const BandConst* __restrict__ bc, int n_band, int nldc,
-                                                       int npol, float* __restrict__ fold) {
+                                                       int npol, T* __restrict__ fold) {
   const int lane = threadIdx.x & (kWave - 1);
   const int row = gim_row(npol), row2 = gim_fold_row(npol), nr = nldc + 1;
   const int64_t groups = (n_band + kFoldBands - 1) / kFoldBands;
@@ -283,8 +284,8 @@ __global__ __launch_bounds__(256) void k_gim_cheb_fold(const double* __restrict_
 #pragma unroll
       for (int q = 0; q < kFoldBands; ++q) {
         if (q < nb) {
-          fold[(b0 + q) * 2 * row2 + i] = float(e[q]);
-          fold[(b0 + q) * 2 * row2 + row2 + i] = float(o[q]);
+          fold[(b0 + q) * 2 * row2 + i] = T(e[q]);
+          fold[(b0 + q) * 2 * row2 + row2 + i] = T(o[q]);
         }
       }
     }
@@ -292,11 +293,16 @@ __global__ __launch_bounds__(256) void k_gim_cheb_fold(const double* __restrict_
 }
 
 hipError_t launch_gim_cheb_fold(const double* tab64, const double* connq, const BandConst* bc, int n_band, int nldc,
-                                int npol, float* fold, hipStream_t s) {
+                                int npol, void* fold, int prec, hipStream_t s) {
   const int64_t groups = (n_band + kFoldBands - 1) / kFoldBands;
   if (groups == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gim_cheb_fold, dim3(grid_for(groups * kWave, 256)), dim3(256), 0, s, tab64, connq, bc, n_band,
-                     nldc, npol, fold);
+  const dim3 grid(grid_for(groups * kWave, 256));
+  if (prec == kPrecFP64)
+    hipLaunchKernelGGL(k_gim_cheb_fold<double>, grid, dim3(256), 0, s, tab64, connq, bc, n_band, nldc, npol,
+                       (double*)fold);
+  else
+    hipLaunchKernelGGL(k_gim_cheb_fold<float>, grid, dim3(256), 0, s, tab64, connq, bc, n_band, nldc, npol,
+                       (float*)fold);
   return hipGetLastError();
 }
 
@@ -529,28 +535,16 @@ template <> __device__ __forceinline__ float band_w<float>(const BandConst* bc, 
 template <> __device__ __forceinline__ double band_w<double>(const BandConst* bc, int m) { return bc->wd[m]; }
 
 template <class T>
-__device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int nldc, int npol,
-                                      const T* __restrict__ tab, const T* __restrict__ rec) {
+__device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int npol, const T* __restrict__ tab) {
   if (z < T(0)) return T(0);
   const T inv1pk = sizeof(T) == 4 ? T(bc->inv1pk) : T(bc->inv1pkd);
   const T c = z * inv1pk;
   const T om = T(1) - c * c;
   if (om <= T(0)) return T(0);
   const T x = T(1) - T(2) * c * c;
-  if constexpr (sizeof(T) == 4) {
-    // float: the band's folded rows E, O (weights and powers of 1 - c^2 inside)
-    const int n2 = npol + kGimFoldPow;
-    return gimenez_cheb_clenshaw(tab, n2, x) + Num<float>::sqrt(om) * gimenez_cheb_clenshaw(tab + gim_row(n2), n2, x);
-  }
-  // double: Jacobi rows and their recurrence, one sum per n
-  const int row = gim_row(npol);
-  T loss = T(0);
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {             // static band-weight indices (nldc <= 4)
-    if (m > nldc) break;
-    loss += band_w<T>(bc, m) * gimenez_power(om, m) * gimenez_clenshaw(tab + m * row, rec + 4 * m * row, npol, x);
-  }
-  return loss;
+  // the band's folded rows E, O (weights and powers of 1 - c^2 inside)
+  const int n2 = npol + kGimFoldPow;
+  return gimenez_cheb_clenshaw(tab, n2, x) + Num<T>::sqrt(om) * gimenez_cheb_clenshaw(tab + gim_row(n2), n2, x);
 }
 
 // Surrogate: lanes whose (z, k) fall in a trusted cell take the network's
@@ -634,15 +628,14 @@ hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab
 __global__ __launch_bounds__(256) void k_gim_ztable(BatchArgs a) {
   const int nodes = a.zin + a.zlimb;
   const int64_t total = (int64_t)a.n_band * nodes, stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t tab_stride = gim_band_stride(false, a.nldc, a.npol);
+  const int64_t tab_stride = gim_band_stride(a.npol);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int bnd = (int)(e / nodes), j = (int)(e % nodes);
     const BandConst* bc = a.bc + bnd;
     const float k = bc->kf;
     const float z = j < a.zin ? (1.0f - k) * j / (a.zin - 1)
                               : (1.0f - k) + 2.0f * k * (j - a.zin) / (a.zlimb - 1);
-    a.ztab[e] = gim_loss<float>(z, bc, a.nldc, a.npol, reinterpret_cast<const float*>(a.gtab) + bnd * tab_stride,
-                                reinterpret_cast<const float*>(a.grec));
+    a.ztab[e] = gim_loss<float>(z, bc, a.npol, reinterpret_cast<const float*>(a.gtab) + bnd * tab_stride);
   }
 }
 
@@ -667,7 +660,7 @@ __device__ __forceinline__ float gim_loss_zinterp(float z, const BandConst* __re
 template <int PREC, int MODEL, class T>
 __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
                                           int bnd, const BatchArgs& a, const T* __restrict__ tb,
-                                          const T* __restrict__ grec, __bf16* act) {
+                                          __bf16* act) {
   static_assert(MODEL != kModelMAKhat || sizeof(T) == 4, "khat runs in the float path");
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   T acc = T(0);
@@ -727,7 +720,7 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
     if (bc->kf < 1.0f) {
       for (int s = 0; s < ns; ++s) acc += gim_loss_zinterp(zb[s * kWave + lane], bc, zt, a.zin, a.zlimb);
     } else {
-      for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.nldc, a.npol, tb, grec);
+      for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.npol, tb);
     }
   } else if constexpr (MODEL == kModelMAKhat) {
     // zb holds three planes of the functions at khat: [3][kZChunk][kWave]
@@ -743,7 +736,7 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
       for (int s = 0; s < ns; ++s) acc += ma_loss<T>(zb[s * kWave + lane], bc);
     }
   } else {
-    for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.nldc, a.npol, tb, grec);
+    for (int s = 0; s < ns; ++s) acc += gim_loss<T>(zb[s * kWave + lane], bc, a.npol, tb);
   }
   return acc;
 }
@@ -765,10 +758,9 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
                     : nullptr;
   const T far_out = T(1e30);
   const T* __restrict__ gtab = reinterpret_cast<const T*>(a.gtab);
-  const T* __restrict__ grec = reinterpret_cast<const T*>(a.grec);
   T* __restrict__ flux = reinterpret_cast<T*>(a.flux);
   const T* __restrict__ obs = reinterpret_cast<const T*>(a.obs);
-  const int64_t tab_stride = gim_band_stride(PREC == kPrecFP64, a.nldc, a.npol);
+  const int64_t tab_stride = gim_band_stride(a.npol);
 
   // Start on the sub-queue of this workgroup's slot (workgroups are handed to
   // the XCDs in turn), move to the next one when it runs dry, stop when all
@@ -923,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
         for (int bnd = b0; bnd < b1; ++bnd) {
           // band constants once per band, by scalar loads
           const BandConst bcv = load_uniform(a.bc + bnd);
-          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride, grec, act),
+          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride, act),
                  bcv, bnd, i, act_lane);
         }
       } else {
@@ -934,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
           for (int s0 = 0; s0 < nss; s0 += kZChunk) {
             const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
             orbit_chunk(tm, dmid, s0, ns, false);
-            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride, grec, act);
+            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride, act);
           }
           finish(acc, bcv, bnd, i, act_lane);
         }
@@ -1031,14 +1023,10 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
-    if (prec == kPrecFP64) {
-      err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab, kPrecFP64, s);
-    } else {
-      // band tables in double, then each band's two folded Chebyshev rows in float
-      err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab64, kPrecFP64, s);
-      if (err == hipSuccess)
-        err = launch_gim_cheb_fold(a.gtab64, a.gconnq, a.bc, a.n_band, a.nldc, a.npol, (float*)a.gtab, s);
-    }
+    // band tables in double, then each band's two folded Chebyshev rows in the working type
+    err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab64, kPrecFP64, s);
+    if (err == hipSuccess)
+      err = launch_gim_cheb_fold(a.gtab64, a.gconnq, a.bc, a.n_band, a.nldc, a.npol, a.gtab, prec, s);
     if (err != hipSuccess) return err;
   }
   if (model == kModelMAInterp && a.ltab) {

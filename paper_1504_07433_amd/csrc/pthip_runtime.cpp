@@ -412,13 +412,9 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
     const size_t nb = std::max<size_t>(1, (size_t)p->n_band);
-    const size_t terms = nb * (b->nldc + 1) * gim_row(npol);       // Jacobi rows, double
-    if (prec == PT_PREC_FP64) {
-      PT_HIP(p->gtab.ensure(terms * sizeof(double)));
-    } else {
-      PT_HIP(p->gtab64.ensure(terms * sizeof(double)));
-      PT_HIP(p->gtab.ensure(nb * (size_t)gim_band_stride(false, b->nldc, npol) * sizeof(float)));
-    }
+    const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
+    PT_HIP(p->gtab64.ensure(nb * (b->nldc + 1) * gim_row(npol) * sizeof(double)));   // Jacobi rows
+    PT_HIP(p->gtab.ensure(nb * (size_t)gim_band_stride(npol) * es));                  // folded rows
   }
   auto tu = g_tuned.find(key);
   if (tu != g_tuned.end()) {
@@ -503,7 +499,6 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     a->gtab64 = (double*)p->gtab64.p;
     a->gconn = (const double*)g->conn.p;
     a->gconnq = (const double*)g->connq.p;
-    a->grec = p->prec == PT_PREC_FP64 ? g->rec64.p : g->rec32.p;
     a->gbcoef = (const double4*)g->bcoef.p;
   }
   return PT_OK;
