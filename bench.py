@@ -30,8 +30,8 @@ sys.path.insert(0, ROOT)
 # unit of work (bench.py --mode units; summary and command in
 # profiles/unit_probes_flops.txt):
 F_ORBIT_ECC = 86.0        # orbit of one in-transit point, e > 0: Kepler, z (float part)
-F_MA_INSIDE = 249.6       # Mandel-Agol functions + limb darkening, z < 1 - k
-F_MA_LIMB = 351.4         # the same, 1 - k < z < 1 + k
+F_MA_INSIDE = 238.7       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 340.4         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8).
 F_POINT, F_EXPOSURE = 5.0, 8.0
@@ -57,7 +57,7 @@ HBM_PEAK = 8.0e12
 # that reads and writes 1 GiB (FETCH_SIZE reads 524319 KiB for 1 GiB read,
 # WRITE_SIZE 1048580 KiB for 1 GiB written).
 VALU_INSTS_PER_LAUNCH = 9.88894e8
-FETCH_KIB, WRITE_KIB = 10783.5, 204912.0
+FETCH_KIB, WRITE_KIB = 11065.8, 204912.0
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524319, 1.0
 
 

@@ -139,7 +139,7 @@ hipError_t launch_gim_cheb_fold(const double* tab64, const double* connq, const 
 hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, int nldc, int npol, float* cheb,
                            hipStream_t s);
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
-                             const double4* bcoef, void* tab, int prec, hipStream_t s);
+                             const double4* bcoef, double* tab, hipStream_t s);
 hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u, int nldc, int nb,
                           int npol, const void* tab, const void* rec, int prec, double* flux,
                           hipStream_t s);

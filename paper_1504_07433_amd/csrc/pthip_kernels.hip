@@ -307,16 +307,12 @@ hipError_t launch_gim_cheb_fold(const double* tab64, const double* connq, const 
 }
 
 hipError_t launch_gim_tables(const double* kvec, double kscalar, int n_band, int nldc, int npol,
-                             const double4* bcoef, void* tab, int prec, hipStream_t s) {
+                             const double4* bcoef, double* tab, hipStream_t s) {
   const int64_t total = (int64_t)n_band * (nldc + 1);
   if (total == 0) return hipSuccess;
   const int grid = grid_for((total + kWave - 1) / kWave * kWave, 256);
-  if (prec == kPrecFP64)
-    hipLaunchKernelGGL(k_gim_band_tables<double>, dim3(grid), dim3(256), 0, s, kvec, kscalar, n_band, nldc,
-                       npol, bcoef, (double*)tab);
-  else
-    hipLaunchKernelGGL(k_gim_band_tables<float>, dim3(grid), dim3(256), 0, s, kvec, kscalar, n_band, nldc,
-                       npol, bcoef, (float*)tab);
+  hipLaunchKernelGGL(k_gim_band_tables<double>, dim3(grid), dim3(256), 0, s, kvec, kscalar, n_band, nldc, npol,
+                     bcoef, tab);
   return hipGetLastError();
 }
 
@@ -528,11 +524,6 @@ __device__ __forceinline__ double ma_loss<double>(double z, const BandConst* __r
   const MaAlpha<double> r = ma_alpha_exact<double>(z, bc->kd);
   return bc->wd[0] * r.le + bc->wd[1] * r.ld + bc->wd[2] * r.ed;
 }
-
-template <class T>
-__device__ __forceinline__ T band_w(const BandConst* bc, int m);
-template <> __device__ __forceinline__ float band_w<float>(const BandConst* bc, int m) { return bc->wf[m]; }
-template <> __device__ __forceinline__ double band_w<double>(const BandConst* bc, int m) { return bc->wd[m]; }
 
 template <class T>
 __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int npol, const T* __restrict__ tab) {
@@ -1024,7 +1015,7 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
     // band tables in double, then each band's two folded Chebyshev rows in the working type
-    err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab64, kPrecFP64, s);
+    err = launch_gim_tables(a.k, 0.0, a.n_band, a.nldc, a.npol, a.gbcoef, a.gtab64, s);
     if (err == hipSuccess)
       err = launch_gim_cheb_fold(a.gtab64, a.gconnq, a.bc, a.n_band, a.nldc, a.npol, a.gtab, prec, s);
     if (err != hipSuccess) return err;

@@ -107,7 +107,7 @@ struct DevBuf {
 // terms {A_j, B_j, C_j, A'_{n,j}} (double) and the Clenshaw recurrence
 // coefficients {A_j, B_j, C_{j+1}, 0} in float and double.
 struct GimTables {
-  DevBuf bcoef, rec32, rec64, conn, connq;
+  DevBuf bcoef, rec64, conn, connq;
 };
 static std::map<std::tuple<int, int, int>, std::unique_ptr<GimTables>> g_gim;
 
@@ -124,7 +124,6 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
   const size_t nr = (size_t)(nldc + 1) * row * 4;     // {A, B, C, 0} per padded term
   std::vector<double> r64(nr, 0.0);
   std::vector<double4> bc(nn);
-  std::vector<float> r32(nr, 0.0f);
   for (int n = 0; n <= nldc; ++n)
     for (int j = 0; j < npol; ++j) {
       double bA, bB, bC;
@@ -134,9 +133,8 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
       gimenez_rec_coef(n, j, &A, &B, &Cn);
       const size_t o = 4 * ((size_t)n * row + j);
       r64[o] = A; r64[o + 1] = B; r64[o + 2] = Cn;
-      r32[o] = float(A); r32[o + 1] = float(B); r32[o + 2] = float(Cn);
     }
-  // Chebyshev coefficients of P_j^(0,nu+1), j < npol, for the float path's rows
+  // Chebyshev coefficients of P_j^(0,nu+1), j < npol, for pt_gimenez's float rows
   const size_t nc = (size_t)row * row;
   std::vector<double> conn((size_t)(nldc + 1) * nc);
   for (int n = 0; n <= nldc; ++n) gimenez_cheb_conn(n, npol, conn.data() + n * nc);
@@ -152,10 +150,8 @@ static pt_status gim_tables(int nldc, int npol, GimTables** out) {
   PT_HIP(hipMemcpy(t->connq.p, connq.data(), connq.size() * sizeof(double), hipMemcpyHostToDevice));
   PT_HIP(t->bcoef.ensure(nn * sizeof(double4)));
   PT_HIP(t->rec64.ensure(nr * sizeof(double)));
-  PT_HIP(t->rec32.ensure(nr * sizeof(float)));
   PT_HIP(hipMemcpy(t->bcoef.p, bc.data(), nn * sizeof(double4), hipMemcpyHostToDevice));
   PT_HIP(hipMemcpy(t->rec64.p, r64.data(), nr * sizeof(double), hipMemcpyHostToDevice));
-  PT_HIP(hipMemcpy(t->rec32.p, r32.data(), nr * sizeof(float), hipMemcpyHostToDevice));
   *out = t.get();
   g_gim[key] = std::move(t);
   return PT_OK;
@@ -626,12 +622,12 @@ pt_status pt_gimenez(const double* z, int64_t n, double k, const double* u, int3
   const size_t terms = (size_t)(nldc + 1) * gim_row(npol);
   PT_HIP(hipMallocAsync(&tab, terms * (8 + (pr == kPrecFP64 ? 0 : 4)), s));
   float* cheb = (float*)((char*)tab + terms * 8);
-  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double4*)g->bcoef.p, tab, kPrecFP64, s);
+  hipError_t e1 = launch_gim_tables(nullptr, k, 1, nldc, npol, (const double4*)g->bcoef.p, (double*)tab, s);
   if (e1 == hipSuccess && pr != kPrecFP64)
     e1 = launch_gim_cheb((const double*)tab, (const double*)g->conn.p, 1, nldc, npol, cheb, s);
   hipError_t e2 = e1 == hipSuccess
                       ? launch_gimenez(z, n, k, u, nldc, nb, npol, pr == kPrecFP64 ? tab : (void*)cheb,
-                                       pr == kPrecFP64 ? g->rec64.p : g->rec32.p, pr, flux, s)
+                                       pr == kPrecFP64 ? g->rec64.p : nullptr, pr, flux, s)
                       : e1;
   hipFreeAsync(tab, s);
   if (e2 != hipSuccess) return fail(PT_ERR_HIP, "gimenez launch: %s", hipGetErrorString(e2));
