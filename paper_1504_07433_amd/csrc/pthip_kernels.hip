@@ -535,7 +535,9 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
   const T x = T(1) - T(2) * c * c;
   // the band's folded rows E, O (weights and powers of 1 - c^2 inside)
   const int n2 = npol + kGimFoldPow;
-  return gimenez_cheb_clenshaw(tab, n2, x) + Num<T>::sqrt(om) * gimenez_cheb_clenshaw(tab + gim_row(n2), n2, x);
+  T se, so;
+  gimenez_cheb_clenshaw2(tab, tab + gim_row(n2), n2, x, &se, &so);
+  return se + Num<T>::sqrt(om) * so;
 }
 
 // Surrogate: lanes whose (z, k) fall in a trusted cell take the network's

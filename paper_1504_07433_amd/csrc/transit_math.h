@@ -936,6 +936,60 @@ PT_HD T gimenez_cheb_clenshaw(const T* cn_, int npol, T x) {
   return x * b1 + (cp[0] - b2);
 }
 
+// Two Chebyshev series over the same x (a band's folded rows E and O) by
+// interleaved Clenshaw recurrences.  Each step reads the next four terms of
+// both rows before it uses the current ones, so that on the GPU the scalar
+// loads of one block overlap the arithmetic of the other.
+template <class T>
+PT_HD void gimenez_cheb_clenshaw2(const T* e_, const T* o_, int n, T x, T* se, T* so) {
+  const int row = gim_row(n);
+  const PT_CONST_AS T* ep = (const PT_CONST_AS T*)e_ + (row - 4);
+  const PT_CONST_AS T* op = (const PT_CONST_AS T*)o_ + (row - 4);
+  const T x2 = x + x;
+  T eb1 = T(0), eb2 = T(0), ob1 = T(0), ob2 = T(0);
+  T ec[4], oc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ec[i] = ep[i];
+    oc[i] = op[i];
+  }
+  for (int blk = row / 4; blk > 1; --blk) {
+    ep -= 4;
+    op -= 4;
+    T en[4], on[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      en[i] = ep[i];
+      on[i] = op[i];
+    }
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      const T e0 = x2 * eb1 + (ec[i] - eb2);
+      const T o0 = x2 * ob1 + (oc[i] - ob2);
+      eb2 = eb1;
+      eb1 = e0;
+      ob2 = ob1;
+      ob1 = o0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ec[i] = en[i];
+      oc[i] = on[i];
+    }
+  }
+#pragma unroll
+  for (int i = 3; i >= 1; --i) {
+    const T e0 = x2 * eb1 + (ec[i] - eb2);
+    const T o0 = x2 * ob1 + (oc[i] - ob2);
+    eb2 = eb1;
+    eb1 = e0;
+    ob2 = ob1;
+    ob1 = o0;
+  }
+  *se = x * eb1 + (ec[0] - eb2);
+  *so = x * ob1 + (oc[0] - ob2);
+}
+
 // (1 - c^2)^(nu+1) for nu = (n+2)/2
 template <class T>
 PT_HD T gimenez_power(T om, int n) {

@@ -56,9 +56,9 @@ extern "C" int gim_fold_loss64(const double* z, int nz, double k, int nldc, int 
   const int n2 = npol + pt::kGimFoldPow;
   for (int q = 0; q < nz; ++q) {
     const double c = z[q] / (1.0 + k), om = 1.0 - c * c, x = 1.0 - 2.0 * c * c;
-    loss[q] = om > 0.0 ? pt::gimenez_cheb_clenshaw<double>(E.data(), n2, x) +
-                             sqrt(om) * pt::gimenez_cheb_clenshaw<double>(O.data(), n2, x)
-                       : 0.0;
+    double se = 0.0, so = 0.0;
+    if (om > 0.0) pt::gimenez_cheb_clenshaw2<double>(E.data(), O.data(), n2, x, &se, &so);
+    loss[q] = om > 0.0 ? se + sqrt(om) * so : 0.0;
   }
   return 0;
 }
