@@ -225,7 +225,7 @@ hipError_t launch_gim_cheb(const double* tab64, const double* conn, int n_band, 
   return hipGetLastError();
 }
 
-// Folded rows of the batch path: per band E[i] and O[i] (gim_fold_row
+// Folded rows of the batch path (Clenshaw order, gim_fold_pos): per band E[i] and O[i] (gim_fold_row
 // coefficients each) with E = sum_{n even} w_n C'_n, O = sum_{n odd} w_n C'_n,
 // C'_n[i] = sum_j T_n[j] M'_n[j][i], M'_n the Chebyshev rows of
 // ((1+x)/2)^q_n P_j^(0,nu+1) and w_n the band's weights; the band's loss is then
@@ -284,8 +284,8 @@ __global__ __launch_bounds__(256) void k_gim_cheb_fold(const double* __restrict_
 #pragma unroll
       for (int q = 0; q < kFoldBands; ++q) {
         if (q < nb) {
-          fold[(b0 + q) * 2 * row2 + i] = T(e[q]);
-          fold[(b0 + q) * 2 * row2 + row2 + i] = T(o[q]);
+          fold[(b0 + q) * 2 * row2 + gim_fold_pos(row2, i, 0)] = T(e[q]);
+          fold[(b0 + q) * 2 * row2 + gim_fold_pos(row2, i, 1)] = T(o[q]);
         }
       }
     }
@@ -536,7 +536,7 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
   // the band's folded rows E, O (weights and powers of 1 - c^2 inside)
   const int n2 = npol + kGimFoldPow;
   T se, so;
-  gimenez_cheb_clenshaw2(tab, tab + gim_row(n2), n2, x, &se, &so);
+  gimenez_cheb_clenshaw2(tab, n2, x, &se, &so);
   return se + Num<T>::sqrt(om) * so;
 }
 

@@ -936,58 +936,71 @@ PT_HD T gimenez_cheb_clenshaw(const T* cn_, int npol, T x) {
   return x * b1 + (cp[0] - b2);
 }
 
-// Two Chebyshev series over the same x (a band's folded rows E and O) by
-// interleaved Clenshaw recurrences.  Each step reads the next four terms of
-// both rows before it uses the current ones, so that on the GPU the scalar
-// loads of one block overlap the arithmetic of the other.
+// A band's two folded rows E and O (row = gim_row(n) coefficients each) are
+// stored in Clenshaw order: block k (k = 0 the highest terms) holds E's terms
+// row-1-4k .. row-4-4k, then O's, eight values, so the recurrence reads one
+// eight-value block per step at increasing addresses.  Position of
+// coefficient i of E (odd = 0) or O (odd = 1):
+PT_HD constexpr int gim_fold_pos(int row, int i, int odd) {
+  return 8 * ((row - 1 - i) / 4) + 4 * odd + (row - 1 - i) % 4;
+}
+
+// One block of both recurrences (four terms each, highest first).
 template <class T>
-PT_HD void gimenez_cheb_clenshaw2(const T* e_, const T* o_, int n, T x, T* se, T* so) {
-  const int row = gim_row(n);
-  const PT_CONST_AS T* ep = (const PT_CONST_AS T*)e_ + (row - 4);
-  const PT_CONST_AS T* op = (const PT_CONST_AS T*)o_ + (row - 4);
-  const T x2 = x + x;
-  T eb1 = T(0), eb2 = T(0), ob1 = T(0), ob2 = T(0);
-  T ec[4], oc[4];
+PT_HD void gimenez_cheb_step8(const T* c, T x2, T& eb1, T& eb2, T& ob1, T& ob2) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    ec[i] = ep[i];
-    oc[i] = op[i];
-  }
-  for (int blk = row / 4; blk > 1; --blk) {
-    ep -= 4;
-    op -= 4;
-    T en[4], on[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      en[i] = ep[i];
-      on[i] = op[i];
-    }
-#pragma unroll
-    for (int i = 3; i >= 0; --i) {
-      const T e0 = x2 * eb1 + (ec[i] - eb2);
-      const T o0 = x2 * ob1 + (oc[i] - ob2);
-      eb2 = eb1;
-      eb1 = e0;
-      ob2 = ob1;
-      ob1 = o0;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ec[i] = en[i];
-      oc[i] = on[i];
-    }
-  }
-#pragma unroll
-  for (int i = 3; i >= 1; --i) {
-    const T e0 = x2 * eb1 + (ec[i] - eb2);
-    const T o0 = x2 * ob1 + (oc[i] - ob2);
+    const T e0 = x2 * eb1 + (c[i] - eb2);
+    const T o0 = x2 * ob1 + (c[4 + i] - ob2);
     eb2 = eb1;
     eb1 = e0;
     ob2 = ob1;
     ob1 = o0;
   }
-  *se = x * eb1 + (ec[0] - eb2);
-  *so = x * ob1 + (oc[0] - ob2);
+}
+
+// The two Chebyshev series E(x) and O(x) of a band's folded rows (Clenshaw
+// order, n coefficients each) by interleaved Clenshaw recurrences.  Blocks
+// alternate between two register sets and the next block is read before the
+// current one is used, so that on the GPU the scalar loads overlap the
+// arithmetic.
+template <class T>
+PT_HD void gimenez_cheb_clenshaw2(const T* blocks, int n, T x, T* se, T* so) {
+  const int nblk = gim_row(n) / 4;
+  const PT_CONST_AS T* bp = (const PT_CONST_AS T*)blocks;
+  const T x2 = x + x;
+  T eb1 = T(0), eb2 = T(0), ob1 = T(0), ob2 = T(0);
+  T a[8], b[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = bp[i];
+  int k = 0;                                        // block held in a
+  for (; k + 2 < nblk; k += 2, bp += 16) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = bp[8 + i];
+    gimenez_cheb_step8(a, x2, eb1, eb2, ob1, ob2);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = bp[16 + i];
+    gimenez_cheb_step8(b, x2, eb1, eb2, ob1, ob2);
+  }
+  if (k + 1 < nblk) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = bp[8 + i];
+    gimenez_cheb_step8(a, x2, eb1, eb2, ob1, ob2);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = b[i];
+  }
+  // the lowest block: terms 3, 2, 1, then term 0 closes the sums
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T e0 = x2 * eb1 + (a[i] - eb2);
+    const T o0 = x2 * ob1 + (a[4 + i] - ob2);
+    eb2 = eb1;
+    eb1 = e0;
+    ob2 = ob1;
+    ob1 = o0;
+  }
+  *se = x * eb1 + (a[3] - eb2);
+  *so = x * ob1 + (a[7] - ob2);
 }
 
 // (1 - c^2)^(nu+1) for nu = (n+2)/2

@@ -41,7 +41,7 @@ extern "C" int gim_fold_loss64(const double* z, int nz, double k, int nldc, int 
   if (nldc < 0 || nldc > 4 || npol < 1 || npol > 512) return 1;
   const int row = pt::gim_row(npol), row2 = pt::gim_fold_row(npol);
   std::vector<double> ap((size_t)(nldc + 1) * npol), tab((size_t)(nldc + 1) * row);
-  std::vector<double> M((size_t)row * row2), E(row2, 0.0), O(row2, 0.0);
+  std::vector<double> M((size_t)row * row2), E(row2, 0.0), O(row2, 0.0), EO(2 * (size_t)row2);
   for (int n = 0; n <= nldc; ++n)
     for (int j = 0; j < npol; ++j) ap[(size_t)n * npol + j] = pt::gimenez_aprime(n, j);
   pt::gimenez_band_table<double>(k, nldc, npol, ap.data(), tab.data());
@@ -53,11 +53,15 @@ extern "C" int gim_fold_loss64(const double* z, int nz, double k, int nldc, int 
       (n & 1 ? O : E)[i] += w[n] * acc;
     }
   }
+  for (int i = 0; i < row2; ++i) {                 // Clenshaw order, as the batch stores them
+    EO[pt::gim_fold_pos(row2, i, 0)] = E[i];
+    EO[pt::gim_fold_pos(row2, i, 1)] = O[i];
+  }
   const int n2 = npol + pt::kGimFoldPow;
   for (int q = 0; q < nz; ++q) {
     const double c = z[q] / (1.0 + k), om = 1.0 - c * c, x = 1.0 - 2.0 * c * c;
     double se = 0.0, so = 0.0;
-    if (om > 0.0) pt::gimenez_cheb_clenshaw2<double>(E.data(), O.data(), n2, x, &se, &so);
+    if (om > 0.0) pt::gimenez_cheb_clenshaw2<double>(EO.data(), n2, x, &se, &so);
     loss[q] = om > 0.0 ? se + sqrt(om) * so : 0.0;
   }
   return 0;
