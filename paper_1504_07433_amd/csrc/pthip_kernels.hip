@@ -685,7 +685,9 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
     } else if (bc->kf >= t.k_lo && bc->kf <= t.k_hi) {
       // the band's pre-combined row; all of the chunk's reads are issued
       // before the first is used
-      const float2* __restrict__ L = a.ltab + (int64_t)bnd * t.nz;
+      // (entry nz - 1 holds its node twice, so the weight does not matter
+      // there; a 32-bit byte offset from the row start)
+      const char* __restrict__ L = reinterpret_cast<const char*>(a.ltab + (int64_t)bnd * t.nz);
       float2 v[kZChunk];
       float wz[kZChunk];
 #pragma unroll
@@ -696,9 +698,9 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
           const float z = zb[s * kWave + lane];
           if (z >= 0.0f && z < bc->onepk) {
             const float fz = z * t.inv_dz;
-            const int iz = min(t.nz - 2, (int)fz);
-            wz[s] = fz - iz;
-            v[s] = L[iz];
+            const uint32_t iz = min(uint32_t(t.nz - 1), (uint32_t)fz);
+            wz[s] = __builtin_amdgcn_fractf(fz);
+            v[s] = *reinterpret_cast<const float2*>(L + iz * 8u);
           }
         }
       }
