@@ -169,6 +169,21 @@ def test_batch_spectrophotometric_small(pt, O):
     assert np.abs(_run(pt, bs, "gimenez", "fp64", u=ug) - refg).max() <= 1e-12
 
 
+@pytest.mark.parametrize("npol,nldc", [(1, 1), (5, 3), (100, 4), (512, 2)])
+def test_batch_gimenez_orders_and_laws(pt, O, npol, nldc):
+    """The batch's folded Chebyshev rows at small and large npol (rows of more
+    than one wavefront of coefficients, one to many Clenshaw blocks) and
+    general laws of 1..4 coefficients, FP32 and FP64, against the oracle."""
+    from paper_1504_07433_amd import workloads as W
+    b = W.config3(n_vec=3, n_band=6, n_exp=300)
+    rng = np.random.default_rng(npol + 10 * nldc)
+    ug = rng.uniform(-0.2, 0.6, (len(b["k"]), nldc)) / nldc
+    say("gimenez batch npol", npol, "nldc", nldc)
+    ref = O.lc_batch(b, model=1, npol=npol, u=ug)
+    assert np.abs(_run(pt, b, "gimenez", "fp32", npol=npol, u=ug) - ref).max() <= TOL32
+    assert np.abs(_run(pt, b, "gimenez", "fp64", npol=npol, u=ug) - ref).max() <= 1e-12
+
+
 def test_batch_uneven_small(pt, O):
     from paper_1504_07433_amd import workloads as W
     b = W.config4(n_lc=48, n_min=50, n_max=3000)
