@@ -235,10 +235,12 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
 #pragma unroll
     for (int it = 0; it < (FIXED_ITERS > 0 ? FIXED_ITERS : 1); ++it) step(false, it == FIXED_ITERS - 1);
   } else {
-    // the first step without the convergence test: a wave nearly always needs
-    // two, and the test and its branch cost about a fifth of a step
+    // the first two steps without the convergence test: a wave nearly always
+    // needs them, and the test with its branch costs about a fifth of a step
+    // (a third unchecked step costs more than the tests it saves)
     step(false, false);
-    for (int it = 1; it < 40; ++it)
+    step(false, false);
+    for (int it = 2; it < 40; ++it)
       if (!step(true, false)) break;
   }
   const T hp = T(0.5 * kPi);
