@@ -91,6 +91,7 @@ template <> struct Num<float> {
 #endif
   }
   static constexpr float cel_tol = 1e-4f;
+  static constexpr int cel_unchecked = 0;        // Gauss steps before the first convergence test
   static constexpr float newton_tol = 2e-7f;     // relative step at convergence
   static constexpr float rot_limit = 0.5f;       // Taylor rotation valid below
   static constexpr int newton_max = 12;
@@ -109,6 +110,7 @@ template <> struct Num<double> {
 #endif
   }
   static constexpr double cel_tol = 1e-10;
+  static constexpr int cel_unchecked = 0;
   static constexpr double newton_tol = 4e-16;
   static constexpr double rot_limit = 0.2;
   static constexpr int newton_max = 40;
@@ -157,6 +159,12 @@ struct NumFast {
   // below what the float rounding of z moves the flux; 3e-5 (3.6e-11) costs
   // 0.3 more Gauss steps per point.
   static constexpr double cel_tol = 3e-4;
+  // The first two Gauss steps run without the convergence test: a wave of
+  // the float path nearly always needs them, and the test with its branch
+  // costs about a fifth of a step (a third unchecked step costs more than the
+  // tests it saves; the double path keeps testing every step, whose extra
+  // straight-line code would cost it occupancy).
+  static constexpr int cel_unchecked = 2;
 };
 
 // sin(h) and 1 - cos(h) by their Taylor series through h^11 / h^12; relative
@@ -235,12 +243,10 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
 #pragma unroll
     for (int it = 0; it < (FIXED_ITERS > 0 ? FIXED_ITERS : 1); ++it) step(false, it == FIXED_ITERS - 1);
   } else {
-    // the first two steps without the convergence test: a wave nearly always
-    // needs them, and the test with its branch costs about a fifth of a step
-    // (a third unchecked step costs more than the tests it saves)
-    step(false, false);
-    step(false, false);
-    for (int it = 2; it < 40; ++it)
+    // Op::cel_unchecked first steps without the convergence test
+    int it = 0;
+    for (; it < Op::cel_unchecked; ++it) step(false, false);
+    for (; it < 40; ++it)
       if (!step(true, false)) break;
   }
   const T hp = T(0.5 * kPi);
