@@ -649,6 +649,32 @@ __device__ __forceinline__ float gim_loss_zinterp(float z, const BandConst* __re
   return (1.0f - w) * zt[zin + i] + w * zt[zin + i + 1];
 }
 
+// Tabulated-model loss summed over the first N subsamples of a chunk, read
+// from a band's pre-combined row (byte base L). All N reads are issued
+// before the first is used; entry nz - 1 holds its node twice, so the weight
+// does not matter there, and the offset from the row start fits 32 bits.
+template <int N>
+__device__ __forceinline__ float interp_rows(const float* zb, int lane, const char* __restrict__ L,
+                                             float onepk, float inv_dz, uint32_t last) {
+  float2 v[N];
+  float wz[N];
+#pragma unroll
+  for (int s = 0; s < N; ++s) {
+    v[s] = make_float2(0.0f, 0.0f);
+    wz[s] = 0.0f;
+    const float z = zb[s * kWave + lane];
+    if (z >= 0.0f && z < onepk) {
+      const float fz = z * inv_dz;
+      wz[s] = __builtin_amdgcn_fractf(fz);
+      v[s] = *reinterpret_cast<const float2*>(L + min(last, (uint32_t)fz) * 8u);
+    }
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int s = 0; s < N; ++s) acc += v[s].x + wz[s] * (v[s].y - v[s].x);
+  return acc;
+}
+
 // Loss of band `bc` summed over the subsamples held in the wave's LDS slice.
 template <int PREC, int MODEL, class T>
 __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
@@ -683,29 +709,16 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
         }
       }
     } else if (bc->kf >= t.k_lo && bc->kf <= t.k_hi) {
-      // the band's pre-combined row; all of the chunk's reads are issued
-      // before the first is used
-      // (entry nz - 1 holds its node twice, so the weight does not matter
-      // there; a 32-bit byte offset from the row start)
+      // the band's pre-combined row, unrolled for the exact chunk length
       const char* __restrict__ L = reinterpret_cast<const char*>(a.ltab + (int64_t)bnd * t.nz);
-      float2 v[kZChunk];
-      float wz[kZChunk];
-#pragma unroll
-      for (int s = 0; s < kZChunk; ++s) {
-        v[s] = make_float2(0.0f, 0.0f);
-        wz[s] = 0.0f;
-        if (s < ns) {
-          const float z = zb[s * kWave + lane];
-          if (z >= 0.0f && z < bc->onepk) {
-            const float fz = z * t.inv_dz;
-            const uint32_t iz = min(uint32_t(t.nz - 1), (uint32_t)fz);
-            wz[s] = __builtin_amdgcn_fractf(fz);
-            v[s] = *reinterpret_cast<const float2*>(L + iz * 8u);
-          }
-        }
+      switch (ns) {
+#define PT_ROWS_CASE(n) \
+  case n: acc += interp_rows<n>(zb, lane, L, bc->onepk, t.inv_dz, uint32_t(t.nz - 1)); break;
+        PT_ROWS_CASE(1) PT_ROWS_CASE(2) PT_ROWS_CASE(3) PT_ROWS_CASE(4) PT_ROWS_CASE(5) PT_ROWS_CASE(6)
+        PT_ROWS_CASE(7) PT_ROWS_CASE(8) PT_ROWS_CASE(9) PT_ROWS_CASE(10) PT_ROWS_CASE(11) PT_ROWS_CASE(12)
+        PT_ROWS_CASE(13) PT_ROWS_CASE(14) PT_ROWS_CASE(15) default: acc += interp_rows<16>(zb, lane, L, bc->onepk, t.inv_dz, uint32_t(t.nz - 1));
+#undef PT_ROWS_CASE
       }
-#pragma unroll
-      for (int s = 0; s < kZChunk; ++s) acc += v[s].x + wz[s] * (v[s].y - v[s].x);
     } else {
       for (int s = 0; s < ns; ++s) acc += ma_loss<float>(zb[s * kWave + lane], bc);
     }
