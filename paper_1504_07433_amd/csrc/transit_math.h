@@ -14,6 +14,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -47,6 +49,7 @@ template <> struct Num<float> {
     return ::sqrtf(x);
 #endif
   }
+  PT_HD static float sqrt2(float x) { return 2.0f * sqrt(x); }
   PT_HD static float rcp(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
     return __builtin_amdgcn_rcpf(x);
@@ -100,6 +103,7 @@ template <> struct Num<float> {
 template <> struct Num<double> {
   PT_HD static double sqrt(double x) { return ::sqrt(x); }
   PT_HD static double rcp(double x) { return 1.0 / x; }
+  PT_HD static double sqrt2(double x) { return 2.0 * ::sqrt(x); }
   PT_HD static double rsqrt(double x) { return 1.0 / ::sqrt(x); }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) {
@@ -151,6 +155,18 @@ struct NumFast {
 #endif
     const double r = fma(-x * y, y, 1.0);    // 1 - x y^2
     return fma(0.5 * y, r, y);
+  }
+  // 2 sqrt(x): the same Newton step scaled by two (bit for bit twice sqrt),
+  // one multiplication fewer than doubling the square root
+  PT_HD static double sqrt2(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+#else
+    const double y = (double)(1.0f / ::sqrtf((float)x));
+#endif
+    const double s = x * y;
+    const double r = fma(-s, s, x);
+    return fma(y, r, s + s);
   }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) { Num<double>::sincos(x, s, c); }
@@ -256,6 +272,52 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
   r.r1 = (b1 + a1 * mu) * d2 * rd;
   r.r2 = (b2 + a2 * mu) * d1 * rd;
   return r;
+}
+
+// c_K K(m) + c_E E(m) + cel(kc, p, a, b) with one transformed integral.  The
+// Gauss steps of cel run the arithmetic-geometric mean of (1, kc) in scaled
+// form (mu_j = 2^j a_j, kk_j = 2^j g_j), and that mean gives the complete
+// integrals of the first and second kind directly (DLMF 19.8.5-19.8.6):
+// K = pi / (2 M(1, kc)) and E = K (1 - sum_n 2^(n-1) c_n^2) with c_0^2 =
+// m = 1 - kc^2 and c_(j+1) = (a_j - g_j) / 2 = (mu_j - kk_j) / 2^(j+1); so only
+// the third-kind integral carries its own (p, a, b) through the steps, and
+// no step needs the product of two p.  The arguments are ckce = c_K + c_E,
+// ce8 = -c_E / 8, sqrt(p) and b / sqrt(p).  On exit after steps 0..J, mu is
+// 2^(J+1) times the next arithmetic mean, whose relative distance from M
+// is about (a_J - g_J)^2 / (16 a_J^2): the same convergence test as cel.
+template <class Op>
+PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a, double bt) {
+  double mu = 1.0, kk = kc, prod = kc;
+  double p = sp, b = bt;
+  double s8 = 4.0 * fma(-kc, kc, 1.0);   // 8 sum 2^(n-1) c_n^2, so far n = 0
+  double w = 2.0;                        // 8 / 2^(j+2): weight of (mu_j - kk_j)^2 in s8
+  auto step = [&](bool check) {
+    const double r = Op::rcp(p);
+    const double g = prod * r;
+    const double f = a;
+    a = fma(b, r, a);
+    b = 2.0 * fma(f, g, b);
+    p = g + p;
+    const double d = mu - kk;
+    s8 = fma(d * w, d, s8);
+    w = 0.5 * w;
+    const double mu_old = mu;
+    mu = mu + kk;
+    if (check && fabs(d) <= mu_old * Op::cel_tol) return false;
+    kk = Op::sqrt2(prod);
+    prod = kk * mu;
+    return true;
+  };
+  int it = 0;
+  for (; it < Op::cel_unchecked; ++it) step(false);
+  for (; it < 40; ++it)
+    if (!step(true)) break;
+  // w = 2^-J now: K = pi 2^J / mu = pi / (mu w), and the third-kind integral
+  // is (pi/2) (b + a mu) / (mu (mu + p)); one reciprocal for both
+  const double mp = mu + p;
+  const double x = fma(ce8, s8, ckce);   // c_K + c_E (1 - sum)
+  const double rd = kPi * Op::rcp(mu * mp * w);
+  return fma(x, mp, 0.5 * w * fma(a, mu, b)) * rd;
 }
 
 
@@ -621,8 +683,10 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 //   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)]
 // with kc = sqrt(1 - m) formed without cancellation.  C_K K + C_E E is one
 // cel with p = 1 and C_P Pi is one cel with p = 1 - n.
-template <class T, int ITERS, class Op = Num<T>>
-PT_HD T ma_elliptic(T z, T k, bool limb) {
+template <class T> struct MaEllTerms { T kc, ck, ce, sp, cp, bt2, pref; };
+
+template <class T, class Op>
+PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
   const T zmk = z - k, zpk = z + k;
   const T z2 = z * z, k2 = k * k;
   const T azmk = fabs(zmk);
@@ -652,8 +716,20 @@ PT_HD T ma_elliptic(T z, T k, bool limb) {
   }
   // C_P = -3 q / a = 3 (z+k) / (z-k) = 3 sign(z-k) (z+k) / |z-k|
   const T cp = T(3) * sgn * zpk * rz;
-  const CelPair<T> r = cel2<T, ITERS, Op>(kc, T(1), ck + ce, ck + ce * kc * kc, sp, cp, bt2);
-  return pref * (r.r1 + r.r2);
+  return MaEllTerms<T>{kc, ck, ce, sp, cp, bt2, pref};
+}
+
+// In double, K and E come from the mean that drives the third-kind integral
+// (cel_agm_ke); otherwise C_K K + C_E E is one cel with p = 1 beside it.
+template <class T, int ITERS, class Op = Num<T>>
+PT_HD T ma_elliptic(T z, T k, bool limb) {
+  const MaEllTerms<T> e = ma_elliptic_terms<T, Op>(z, k, limb);
+  if constexpr (std::is_same<T, double>::value && ITERS == 0) {
+    return e.pref * cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.cp, e.bt2);
+  } else {
+    const CelPair<T> r = cel2<T, ITERS, Op>(e.kc, T(1), e.ck + e.ce, e.ck + e.ce * e.kc * e.kc, e.sp, e.cp, e.bt2);
+    return e.pref * (r.r1 + r.r2);
+  }
 }
 
 // lambda_e and eta_1 in the limb region, with the square root of
