@@ -815,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
       step_f = float(w * inv_nss);
       base_f = float(w * (0.5 * inv_nss - 0.5));
     } else {
-      oc = a.oc[lc];
+      oc = load_uniform(a.oc + lc);
     }
     const bool orbit_ok = F32 ? of.valid != 0 : oc.valid != 0;
 

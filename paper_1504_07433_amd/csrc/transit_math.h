@@ -778,23 +778,13 @@ PT_HD void ellke(T m, T* K, T* E) {
   *E = r.r2;
 }
 
-// All cases of the Mandel & Agol table in the working type (double in
-// practice).  Equalities are taken after snapping |z-k| < 1e-9,
-// |z-(1-k)| < 1e-12 (k < 1/2), z < 1e-12 and |k-1/2| < 1e-12 onto them; for
-// k > 1/2 a distance within 1e-12 of 1-k is moved to 1-k+1e-12, where the
-// limb formula is still finite.
+// The cases of the Mandel & Agol table on a boundary of measure zero (star
+// covered, centred planet, z = k, z = 1 - k inside the disc), after the
+// snapping of ma_alpha_exact.  Out of line: the bulk evaluation need not hold
+// their registers.
 template <class T>
-PT_HD MaAlpha<T> ma_alpha_exact(T z, T k) {
+__host__ __device__ __attribute__((noinline)) MaAlpha<T> ma_alpha_special(T z, T k) {
   MaAlpha<T> r{T(0), T(0), T(0)};
-  if (!(z >= T(0))) return r;
-  if (fabs(k - T(0.5)) < T(1e-12)) k = T(0.5);
-  if (z < T(1e-12)) z = T(0);
-  if (fabs(z - k) < T(1e-9)) z = k;
-  if (z >= T(1) + k) return r;
-  if (fabs(z - (T(1) - k)) < T(1e-12)) {
-    if (k < T(0.5)) z = T(1) - k;
-    else if (k > T(0.5) && k < T(1)) z = T(1) - k + T(1e-12);
-  }
   const T k2 = k * k, z2 = z * z;
   const T third = T(1.0 / 3.0), tt = T(2.0 / 3.0);
   if (k >= T(1) && z <= k - T(1)) {            // star fully covered
@@ -807,12 +797,6 @@ PT_HD MaAlpha<T> ma_alpha_exact(T z, T k) {
     r.le = k2;
     r.ld = -tt * om * Num<T>::sqrt(om) + tt;
     r.ed = eta2;
-    return r;
-  }
-  const bool limb = z > T(1) - k || (k > T(0.5) && z >= T(1) - k);
-  if (limb && z != k) {                         // partial overlap of the limb
-    ma_limb_terms(z, k, &r.le, &r.ed);
-    r.ld = ma_elliptic<T, 0>(z, k, true) + (z < k ? tt : T(0));
     return r;
   }
   if (z == k) {
@@ -835,13 +819,43 @@ PT_HD MaAlpha<T> ma_alpha_exact(T z, T k) {
     }
     return r;
   }
+  // z == 1 - k with k < 1/2: lambda_5, eta_2
   r.le = k2;
   r.ed = eta2;
-  if (z == T(1) - k) {                          // lambda_5 (k < 1/2)
-    r.ld = T(2.0 / (3.0 * kPi)) * acos(T(1) - T(2) * k)
-           - T(4.0 / (9.0 * kPi)) * (T(3) + T(2) * k - T(8) * k2) * Num<T>::sqrt(k * (T(1) - k));
+  r.ld = T(2.0 / (3.0 * kPi)) * acos(T(1) - T(2) * k)
+         - T(4.0 / (9.0 * kPi)) * (T(3) + T(2) * k - T(8) * k2) * Num<T>::sqrt(k * (T(1) - k));
+  return r;
+}
+
+// All cases of the Mandel & Agol table in the working type (double in
+// practice).  Equalities are taken after snapping |z-k| < 1e-9,
+// |z-(1-k)| < 1e-12 (k < 1/2), z < 1e-12 and |k-1/2| < 1e-12 onto them; for
+// k > 1/2 a distance within 1e-12 of 1-k is moved to 1-k+1e-12, where the
+// limb formula is still finite.
+template <class T>
+PT_HD MaAlpha<T> ma_alpha_exact(T z, T k) {
+  MaAlpha<T> r{T(0), T(0), T(0)};
+  if (!(z >= T(0))) return r;
+  if (fabs(k - T(0.5)) < T(1e-12)) k = T(0.5);
+  if (z < T(1e-12)) z = T(0);
+  if (fabs(z - k) < T(1e-9)) z = k;
+  if (z >= T(1) + k) return r;
+  if (fabs(z - (T(1) - k)) < T(1e-12)) {
+    if (k < T(0.5)) z = T(1) - k;
+    else if (k > T(0.5) && k < T(1)) z = T(1) - k + T(1e-12);
+  }
+  const bool limb = z > T(1) - k || (k > T(0.5) && z >= T(1) - k);
+  if ((k >= T(1) && z <= k - T(1)) || z == T(0) || z == k || (!limb && z == T(1) - k))
+    return ma_alpha_special(z, k);
+  const T k2 = k * k;
+  const T tt = T(2.0 / 3.0);
+  if (limb) {                                   // partial overlap of the limb
+    ma_limb_terms(z, k, &r.le, &r.ed);
+    r.ld = ma_elliptic<T, 0>(z, k, true) + (z < k ? tt : T(0));
     return r;
   }
+  r.le = k2;
+  r.ed = T(0.5) * k2 * (k2 + T(2) * z * z);
   r.ld = ma_elliptic<T, 0>(z, k, false) + (z < k ? tt : T(0));   // lambda_2, eta_2
   return r;
 }
