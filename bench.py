@@ -30,8 +30,8 @@ sys.path.insert(0, ROOT)
 # unit of work (bench.py --mode units; summary and command in
 # profiles/unit_probes_flops.txt):
 F_ORBIT_ECC = 86.0        # orbit of one in-transit point, e > 0: Kepler, z (float part)
-F_MA_INSIDE = 239.8       # Mandel-Agol functions + limb darkening, z < 1 - k
-F_MA_LIMB = 334.5         # the same, 1 - k < z < 1 + k
+F_MA_INSIDE = 214.6       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 307.0         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8).
 F_POINT, F_EXPOSURE = 5.0, 8.0
@@ -43,8 +43,8 @@ F_POINT, F_EXPOSURE = 5.0, 8.0
 # in-transit point (phase, one Kepler solve, series coefficients, flux).  The
 # probes run at series order 4; order-5 light curves spend ~4 flops more per
 # point and ~20 more per exposure, which the model does not charge.
-F_SER_INSIDE = 201.0
-F_SER_LIMB = 287.0
+F_SER_INSIDE = 176.0
+F_SER_LIMB = 262.0
 F_SER_EXPOSURE = 228.0
 SERIES_NSS = (4, 16)
 PEAK_ALU = 78.6e12        # 256 CU x 64 FMA lanes x 2 flops x 2.4 GHz (FP32 non-packed = FP64)
@@ -56,8 +56,8 @@ HBM_PEAK = 8.0e12
 # WRITE_SIZE (KiB) scaled by what the counters read for an elementwise kernel
 # that reads and writes 1 GiB (FETCH_SIZE reads 524319 KiB for 1 GiB read,
 # WRITE_SIZE 1048580 KiB for 1 GiB written).
-VALU_INSTS_PER_LAUNCH = 9.35311e8
-FETCH_KIB, WRITE_KIB = 11039.6, 204912.0
+VALU_INSTS_PER_LAUNCH = 8.71723e8
+FETCH_KIB, WRITE_KIB = 10920.7, 204912.0
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524319, 1.0
 
 
