@@ -415,6 +415,24 @@ def test_interpolated_model_matches_oracle(pt, O):
     assert np.abs(got - ref).max() <= TOL32
 
 
+def test_interpolated_rows_every_chunk_length(pt, O):
+    """Per-band table rows are read by code unrolled for the exact number of
+    subsamples in a chunk (1..16; more than 16 run in chunks of 16 and a
+    remainder): light curves with 1..20 subsamples against the oracle's
+    tabulated variant."""
+    from paper_1504_07433_amd import workloads as W
+    b = W.config4(seed=7, n_lc=20, n_min=1500, n_max=2000)
+    b["nss"][:] = np.arange(1, 21, dtype=np.int32)
+    k_lo, k_hi, nk, nz = float(b["k"].min()), float(b["k"].max()), 64, 512
+    pt.ma_table_set(k_lo, k_hi, nk, nz)
+    tab = O.ma_table(k_lo, k_hi, nk, nz)
+    say("chunk lengths: bands", len(b["k"]), "points", W.n_points(b))
+    ref = O.lc_batch_ma_variant(b, "interp", tab, k_lo, k_hi)
+    got = _run(pt, b, "ma_interp", "fp32")
+    assert np.abs(got - ref).max() <= TOL32
+    assert np.count_nonzero(ref < 1.0) > len(ref) // 10     # the transits are sampled
+
+
 def test_interpolated_model_many_bands_matches_oracle(pt, O):
     """65536 passbands x 2048 z nodes exceed the size kept for per-band rows,
     so the kernel interpolates the shared (k, z) table directly."""
