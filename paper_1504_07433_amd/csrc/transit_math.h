@@ -681,8 +681,9 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 // with lambda_1) and inside the disc (z < 1-k, k < 1/2; lambda_2) the
 // elliptic combination is
 //   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)]
-// with kc = sqrt(1 - m) formed without cancellation.  C_K K + C_E E is one
-// cel with p = 1 and C_P Pi is one cel with p = 1 - n.
+// with kc = sqrt(1 - m) formed without cancellation.  C_P Pi is one cel with
+// p = 1 - n; C_K K + C_E E is a second cel with p = 1, or, in double, comes
+// from the mean that the first one runs (ma_elliptic).
 template <class T> struct MaEllTerms { T kc, ck, ce, sp, cp, bt2, pref; };
 
 template <class T, class Op>
