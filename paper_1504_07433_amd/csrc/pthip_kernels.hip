@@ -752,8 +752,12 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
 // LOGL = false: write the flux.  LOGL = true: accumulate the squared
 // normalised residuals against the observed flux instead and write one
 // partial sum per tile (summed per light curve by k_loglike_reduce).
+// The FP64 Mandel-Agol kernel is held to 128 registers: four waves per SIMD
+// instead of three, for about 30 spill slots, nearly all touched once per
+// tile rather than per point.
 template <int PREC, int MODEL, bool LOGL>
-__global__ __launch_bounds__(kBlock) void k_lc_batch(BatchArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 1, 8))) void k_lc_batch(BatchArgs a) {
   using T = typename std::conditional<PREC == kPrecFP64, double, float>::type;
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   extern __shared__ unsigned char lds_raw[];
