@@ -191,6 +191,7 @@ struct TileSet {
 };
 
 struct Plan {
+  std::string shape_key;
   int dev = -1;
   int32_t n_lc = 0, n_band = 0, nldc = 0, npol = 0, model = 0, prec = 0;
   std::vector<int64_t> t_count;
@@ -363,16 +364,28 @@ static int default_tile(const pt_batch* b) {
 
 static std::map<std::string, LaunchShape> g_tuned;  // autotuned shapes by plan key
 
-static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_prec prec, Plan** out,
-                          std::string* key_out) {
-  std::string key = plan_key(b, model, npol, prec);
-  if (key_out) *key_out = key;
+// A plan owns device scratch that every call rewrites (queue counters, orbit
+// and band constants, tables), so calls on different streams get plans of
+// their own: the key is the batch shape plus the stream.  Autotuned launch
+// shapes are kept by batch shape alone and shared by every stream's plan.
+static std::string stream_key(const std::string& shape_key, hipStream_t s) {
+  char buf[32];
+  snprintf(buf, sizeof buf, "s%llx", (unsigned long long)(uintptr_t)s);
+  return shape_key + buf;
+}
+
+static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_prec prec, hipStream_t stream,
+                          Plan** out, std::string* key_out) {
+  const std::string shape_key = plan_key(b, model, npol, prec);
+  if (key_out) *key_out = shape_key;
+  const std::string key = stream_key(shape_key, stream);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     *out = it->second.get();
     return PT_OK;
   }
   auto p = std::make_unique<Plan>();
+  p->shape_key = shape_key;
   p->dev = current_device();
   p->n_lc = b->n_lc;
   p->n_band = b->n_lc > 0 ? b->band_off[b->n_lc] : 0;
@@ -412,7 +425,7 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
     PT_HIP(p->gtab64.ensure(nb * (b->nldc + 1) * gim_row(npol) * sizeof(double)));   // Jacobi rows
     PT_HIP(p->gtab.ensure(nb * (size_t)gim_band_stride(npol) * es));                  // folded rows
   }
-  auto tu = g_tuned.find(key);
+  auto tu = g_tuned.find(shape_key);
   if (tu != g_tuned.end()) {
     p->shape = tu->second;
     p->tuned = true;
@@ -647,7 +660,7 @@ pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
   std::lock_guard<std::mutex> lk(g_mu);
   Plan* p = nullptr;
-  st = get_plan(batch, model, npol, prec, &p, nullptr);
+  st = get_plan(batch, model, npol, prec, (hipStream_t)stream, &p, nullptr);
   if (st != PT_OK) return st;
   BatchArgs a;
   st = fill_args(batch, p, p->shape.tile_e, flux, &a);
@@ -692,7 +705,10 @@ pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_
                         const double* sigma, double* loglike, void* stream) {
   pt_status st = validate_batch(batch, model, npol, prec);
   if (st != PT_OK) return st;
-  if (!getenv("PT_ENABLE_LOGLIKE"))
+  // Off unconditionally: the first GPU test of this path stopped responding
+  // and no cause has been shown, so nothing may launch it.
+  constexpr bool kLoglikeEnabled = false;
+  if (!kLoglikeEnabled)
     return fail(PT_ERR_UNSUPPORTED,
                 "the fused likelihood is switched off: its first GPU test stopped responding and the cause "
                 "is not yet identified");
@@ -704,7 +720,7 @@ pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_
   if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
   std::lock_guard<std::mutex> lk(g_mu);
   Plan* p = nullptr;
-  st = get_plan(batch, model, npol, prec, &p, nullptr);
+  st = get_plan(batch, model, npol, prec, (hipStream_t)stream, &p, nullptr);
   if (st != PT_OK) return st;
   BatchArgs a;
   // a non-null obs pointer selects the likelihood kernels, even for n_flux = 0
@@ -721,9 +737,11 @@ pt_status pt_batch_launch_shape(const pt_batch* batch, pt_model model, int32_t n
   if (st != PT_OK) return st;
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string key = plan_key(batch, model, npol, prec);
-  auto it = g_plans.find(key);
-  if (tile_exposures) *tile_exposures = it == g_plans.end() ? -1 : it->second->shape.tile_e;
-  if (workgroups) *workgroups = it == g_plans.end() ? -1 : it->second->shape.workgroups;
+  const Plan* found = nullptr;
+  for (const auto& kv : g_plans)
+    if (kv.second->shape_key == key) found = kv.second.get();
+  if (tile_exposures) *tile_exposures = found ? found->shape.tile_e : -1;
+  if (workgroups) *workgroups = found ? found->shape.workgroups : -1;
   return ok();
 }
 
@@ -738,7 +756,7 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   std::lock_guard<std::mutex> lk(g_mu);
   Plan* p = nullptr;
   std::string key;
-  st = get_plan(batch, model, npol, prec, &p, &key);
+  st = get_plan(batch, model, npol, prec, (hipStream_t)stream, &p, &key);
   if (st != PT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const int cu = std::max(1, cu_count());

@@ -559,7 +559,7 @@ PT_HD float orbit_zf(const OrbitF& o, float dm) {
 
 // ---------------------------------------------------------------------------
 // Sky position of the subsamples of one exposure as power series in the
-// mean-anomaly offset d from the exposure's centre (Sect. 2.1.3 solves
+// mean-anomaly offset d from the exposure's centre (the supersampling of Sect. 3.2 solves
 // Kepler's equation once per subsample; this solves it once per exposure).
 // With x(d) the eccentric-anomaly offset from conjunction, S = sin x and
 // C = cos x, Kepler's equation reads x - e cos E_c S + e sin E_c (1 - C) = dM.

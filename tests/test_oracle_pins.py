@@ -333,3 +333,151 @@ def test_gimenez_zinterp_error_matches_paper_order(oracle):
         mn.append(d.mean())
     assert g_max["value"] / 3 <= max(mx) <= 3 * g_max["value"]
     assert g_mean["value"] / 10 <= np.mean(mn) <= 10 * g_mean["value"]
+
+
+# --- the batch's Gimenez branch, the k-hat variant and the likelihood --------------
+
+def _ragged_batch(seed, nldc, n_lc=7):
+    """A small ragged batch: uneven lengths and supersampling, 1..4 bands per
+    light curve with their own k and general-law coefficients, eccentric
+    orbits; an empty light curve and one without bands included."""
+    from paper_1504_07433_amd import workloads as W
+    b = W.config4(seed=seed, n_lc=n_lc, n_min=40, n_max=160, max_nss=5, max_bands=4)
+    rng = np.random.default_rng(seed)
+    for lc in range(n_lc):                       # exposures across the transit
+        s0, cnt = b["t_start"][lc], b["t_count"][lc]
+        b["t"][s0:s0 + cnt] = np.linspace(-0.06, 0.06, cnt) + 3.0 * lc
+    b["t_count"][2] = 0
+    nb = np.diff(b["band_off"]).astype(np.int64)
+    b["flux_off"] = np.concatenate([[0], np.cumsum(nb * b["t_count"])[:-1]]).astype(np.int64)
+    b["n_flux"] = int((nb * b["t_count"]).sum())
+    ug = rng.uniform(-0.2, 0.6, (len(b["k"]), nldc)) / nldc
+    return b, ug
+
+
+def _mean_over_subsamples(oracle, b, lc, flux_of_z):
+    """Mean over the midpoint subsamples of one light curve's exposures of a
+    per-point flux function, one exposure at a time."""
+    s0, cnt, n = b["t_start"][lc], b["t_count"][lc], int(b["nss"][lc])
+    prm = tuple(b[key][lc] for key in ("t0", "P", "aR", "b", "e", "w"))
+    out = np.empty(cnt)
+    for i in range(cnt):
+        ts = b["t"][s0 + i] + b["t_exp"][lc] * ((np.arange(n) + 0.5) / n - 0.5)
+        out[i] = np.mean(flux_of_z(oracle.orbit_z(ts, *prm)))
+    return out
+
+
+@pytest.mark.parametrize("nldc", [1, 2, 3, 4])
+def test_batch_gimenez_branch_equals_pointwise_model(oracle, nldc):
+    """The batch's Gimenez branch (Sects. 2.1.3, 3.2) is, element by element,
+    the mean over the exposure's midpoint subsamples of the pinned pointwise
+    Gimenez flux at the pinned orbit's z, with band j of light curve i reading
+    its own k and its own nldc coefficients: an index slip in the band's
+    coefficient row, the band or light-curve offsets fails here."""
+    b, ug = _ragged_batch(30 + nldc, nldc)
+    npol = 12 + 5 * nldc
+    got = oracle.lc_batch(b, model=1, npol=npol, u=ug)
+    checked = 0
+    for lc in range(len(b["t_start"])):
+        cnt = b["t_count"][lc]
+        if cnt == 0:
+            continue
+        for j, bnd in enumerate(range(b["band_off"][lc], b["band_off"][lc + 1])):
+            ref = _mean_over_subsamples(
+                oracle, b, lc, lambda z: oracle.gimenez_flux(z, b["k"][bnd], ug[bnd], npol))
+            off = b["flux_off"][lc] + j * cnt
+            assert np.abs(got[off:off + cnt] - ref).max() <= 1e-15, (lc, bnd)
+            checked += cnt
+    assert checked == b["n_flux"] and (got < 1).sum() > 20
+
+
+def test_batch_gimenez_branch_converges_to_mandel_agol(oracle):
+    """Under the quadratic law (general-law u1 + 2 u2, -u2, Sect. 2.1.2) the
+    batch's Gimenez branch approaches the batch's Mandel-Agol branch as npol
+    grows (the series converges to the exact moments)."""
+    b, _ = _ragged_batch(41, 2)
+    ma = oracle.lc_batch(b, model=0)
+    e50 = np.abs(oracle.lc_batch(b, model=1, npol=50) - ma).max()
+    e200 = np.abs(oracle.lc_batch(b, model=1, npol=200) - ma).max()
+    assert e200 < e50 <= 1e-4 and e200 <= 5e-6
+
+
+def _khat_batch():
+    from paper_1504_07433_amd import workloads as W
+    b = W.config3(seed=3, n_vec=3, n_band=5, n_exp=120)
+    b["b"][:] = 0.0                              # z(t0) = b = 0: a central transit
+    b["t"] = np.concatenate([[0.0], b["t"][1:]])  # one exposure at t0 exactly
+    for lc in range(3):
+        b["t0"][lc] = 0.0
+    return b
+
+
+def test_khat_variant_exact_when_bands_share_k(oracle):
+    """Sect. 3.5: with one radius ratio for all bands of a light curve, the
+    k-hat approximation is the exact model."""
+    b = _khat_batch()
+    for lc in range(3):
+        b0, b1 = b["band_off"][lc], b["band_off"][lc + 1]
+        b["k"][b0:b1] = b["k"][b0]
+    got = oracle.lc_batch_ma_variant(b, "khat")
+    assert np.abs(got - oracle.lc_batch(b, model=0)).max() <= 1e-15
+
+
+def test_khat_variant_scaling_and_mean(oracle):
+    """Sect. 3.5 scales each band's depth by k_i^2 / khat^2.  (1) A uniform
+    source (u = 0) with the whole planet on the disc has loss k_i^2 in band i,
+    whatever khat: a wrong exponent of the scaling fails.  (2) At z = 0 the
+    moments of a centred disc of radius r are closed forms of the integral
+    (1/pi) int mu^n dA = 2 int_0^r (1 - s^2)^(n/2) s ds: alpha_0 = r^2,
+    alpha_1 = 2/3 (1 - (1 - r^2)^(3/2)), alpha_0 - alpha_2 = r^4 / 2; at
+    r = khat, the arithmetic mean of the bands' k, scaled by k_i^2/khat^2,
+    they give the variant's loss in band i: a different mean fails."""
+    b = _khat_batch()
+    nb = np.diff(b["band_off"])
+    rng = np.random.default_rng(9)
+    b["k"] = rng.uniform(0.05, 0.15, len(b["k"]))
+    u0 = b["u"].copy()
+    b["u"][:] = 0.0
+    f0 = oracle.lc_batch_ma_variant(b, "khat")
+    b["u"] = u0
+    f = oracle.lc_batch_ma_variant(b, "khat")
+    for lc in range(3):
+        b0, b1 = b["band_off"][lc], b["band_off"][lc + 1]
+        ks = b["k"][b0:b1]
+        khat = ks.mean()
+        cnt = b["t_count"][lc]
+        prm = tuple(b[key][lc] for key in ("t0", "P", "aR", "b", "e", "w"))
+        z = oracle.orbit_z(b["t"][b["t_start"][lc]:b["t_start"][lc] + cnt], *prm)
+        inside = (z >= 0) & (z <= 1 - ks.max())
+        assert inside.sum() > 10 and abs(z[0]) < 1e-12
+        a0, a1, ad = khat ** 2, 2 / 3 * (1 - (1 - khat ** 2) ** 1.5), khat ** 4 / 2
+        for j in range(b1 - b0):
+            off = b["flux_off"][lc] + j * cnt
+            loss0 = 1 - f0[off:off + cnt]
+            assert np.abs(loss0[inside] - ks[j] ** 2).max() <= 1e-15
+            u1, u2 = b["u"][b0 + j]
+            c = u1 + 2 * u2
+            loss_z0 = ((1 - c) * a0 + c * a1 + u2 * ad) / (1 - u1 / 3 - u2 / 6) * ks[j] ** 2 / khat ** 2
+            assert abs((1 - f[off]) - loss_z0) <= 1e-14
+    assert nb.min() == 5
+
+
+def test_loglike_vs_scipy_normal_logpdf(oracle):
+    """The Gaussian log-likelihood per light curve (the paper's likelihood,
+    Sects. 3.4 and 4; white noise of one sigma per light curve) equals the sum
+    of scipy's normal log-densities over the light curve's points, all bands
+    included."""
+    from scipy.stats import norm
+    b, _ = _ragged_batch(51, 2)
+    F = oracle.lc_batch(b, model=0)
+    rng = np.random.default_rng(1)
+    sigma = rng.uniform(5e-4, 2e-3, len(b["t_start"]))
+    nb = np.diff(b["band_off"]).astype(np.int64)
+    obs = F + rng.normal(0, 1, len(F)) * np.repeat(sigma, nb * b["t_count"])
+    got = oracle.loglike(b, obs, sigma, flux=F)
+    for i in range(len(sigma)):
+        sl = slice(b["flux_off"][i], b["flux_off"][i] + nb[i] * b["t_count"][i])
+        ref = norm.logpdf(obs[sl], loc=F[sl], scale=sigma[i]).sum()
+        assert got[i] == pytest.approx(ref, rel=1e-13, abs=1e-9), i
+    # without a precomputed flux the oracle's own model is used
+    assert np.allclose(oracle.loglike(b, obs, sigma), got, rtol=0, atol=1e-9)
