@@ -210,6 +210,31 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
 pt_status pt_batch_launch_shape(const pt_batch* batch, pt_model model, int32_t npol,
                                 pt_prec prec, int32_t* tile_exposures, int32_t* workgroups);
 
+/* pt_lc_batch for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same output as pt_lc_batch, with every scratch
+ * buffer of the call (tile queue counters, device copies of the shape
+ * arrays, the tile list, per-light-curve orbit and per-band constants) in
+ * one static device array of 16 MiB that each GPU the library runs on holds
+ * until the process ends.  Nothing is allocated on the device, no plan is
+ * cached and no graph is captured: each call copies the shape arrays and
+ * the tile list (at most 8 MiB, from a static host staging area) on
+ * `stream` and launches the kernels directly.
+ *   model   PT_MODEL_MA_QUAD only (else PT_ERR_UNSUPPORTED)
+ *   prec    PT_PREC_FP32 or PT_PREC_FP64 (else PT_ERR_UNSUPPORTED)
+ *   batch, flux as for pt_lc_batch
+ * Limits: about 272 bytes per light curve, 104 per passband and 16 per tile
+ * (each part rounded up to 256 bytes, plus 1 KiB of counters) must fit the
+ * 16 MiB, and the shape arrays with the tile list the 8 MiB staging area;
+ * tiles are made longer until the tile list fits, and a batch that does not
+ * fit even then (e.g. more than about 160,000 passbands) gives PT_ERR_ARG
+ * with the sizes, before any HIP call.
+ * Every call on one GPU shares that GPU's array: calls on one GPU whose
+ * executions overlap (different streams, or threads) race and give wrong
+ * flux; serialise them.  Errors: as pt_lc_batch. */
+pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec prec, void* flux,
+                              void* stream);
+
 /* ---------------------------------------------------------------------------
  * Learned surrogate of the three Mandel-Agol functions (lambda_e,
  * lambda_d + 2/3 Theta(k-z), eta_d) = (alpha_0, alpha_1, alpha_0 - alpha_2)

@@ -557,6 +557,80 @@ static pt_status run_plan(Plan* p, const BatchArgs& a, int workgroups, hipStream
   return PT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batch without allocation (pt_lc_batch_noalloc).  Every scratch buffer of
+// the call -- queue counters, the device copies of the shape arrays, the tile
+// list, the orbit and band constants -- lives in one file-scope device array.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// address on each GPU is taken once per device with hipGetSymbolAddress, and
+// only that address reaches kernels and copies.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = size_t(16) << 20;        // the whole array
+constexpr size_t kNoAllocStageBytes = size_t(8) << 20;    // shape arrays + tile list
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+  unsigned char* ptr = nullptr;   // device address of `scratch` on this GPU
+  hipEvent_t staged = nullptr;    // end of the last copy out of the host staging area
+  bool ready = false;
+};
+static NoAllocDevice g_noalloc[16];
+// Host staging area of the copied shape arrays and tile list (one, shared by
+// every device; the next call waits for the previous copy out of it).
+alignas(256) static unsigned char g_noalloc_stage[kNoAllocStageBytes];
+static int g_noalloc_last_dev = -1;
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte offsets of the parts of `scratch`; [t_start, stage_end) is the staged
+// (host-copied) part, in the same layout as the host staging area.
+struct NoAllocLayout {
+  size_t t_start, t_count, nss, band_off, flux_off, tiles, stage_end, oc, ocf, bc, end;
+};
+
+static NoAllocLayout noalloc_layout(int64_t n_lc, int64_t n_band, int64_t n_tiles) {
+  NoAllocLayout L;
+  size_t o = align256(kQueues * kQueueStride * sizeof(unsigned int));
+  L.t_start = o;  o = align256(o + (size_t)n_lc * 8);
+  L.t_count = o;  o = align256(o + (size_t)n_lc * 8);
+  L.nss = o;      o = align256(o + (size_t)n_lc * 4);
+  L.band_off = o; o = align256(o + (size_t)(n_lc + 1) * 4);
+  L.flux_off = o; o = align256(o + (size_t)n_lc * 8);
+  L.tiles = o;    o = align256(o + (size_t)n_tiles * sizeof(TileDesc));
+  L.stage_end = o;
+  L.oc = o;       o = align256(o + (size_t)n_lc * sizeof(OrbitConst));
+  L.ocf = o;      o = align256(o + (size_t)n_lc * sizeof(OrbitF));
+  L.bc = o;       o = align256(o + (size_t)n_band * sizeof(BandConst));
+  L.end = o;
+  return L;
+}
+
+static int64_t count_tiles(const pt_batch* b, int tile_e) {
+  int64_t n = 0;
+  for (int32_t i = 0; i < b->n_lc; ++i)
+    if (b->band_off[i + 1] > b->band_off[i]) n += (b->t_count[i] + tile_e - 1) / tile_e;
+  return n;
+}
+
+// The tile list of build_tiles (longest first, ties in light-curve order),
+// written into the staging area and sorted in place.
+static void noalloc_tiles(const pt_batch* b, int tile_e, TileDesc* out, int64_t n_tiles) {
+  int64_t j = 0;
+  for (int32_t lc = 0; lc < b->n_lc; ++lc) {
+    if (b->band_off[lc + 1] == b->band_off[lc]) continue;
+    for (int64_t e0 = 0; e0 < b->t_count[lc]; e0 += tile_e)
+      out[j++] = TileDesc{lc, (int32_t)e0, (int32_t)std::min<int64_t>(tile_e, b->t_count[lc] - e0), 0};
+  }
+  auto work = [b](const TileDesc& t) {
+    return double((t.ne + kWave - 1) / kWave) * b->nss[t.lc] * (b->band_off[t.lc + 1] - b->band_off[t.lc] + 1.0);
+  };
+  std::sort(out, out + n_tiles, [&](const TileDesc& x, const TileDesc& y) {
+    const double wx = work(x), wy = work(y);
+    if (wx != wy) return wx > wy;
+    return x.lc != y.lc ? x.lc < y.lc : x.e0 < y.e0;
+  });
+}
+
 }  // namespace pt
 
 using namespace pt;
@@ -822,6 +896,98 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
     strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
+  return ok();
+}
+
+pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec prec, void* flux, void* stream) {
+  if (model != PT_MODEL_MA_QUAD)
+    return fail(PT_ERR_UNSUPPORTED, "pt_lc_batch_noalloc covers PT_MODEL_MA_QUAD only");
+  if (prec != PT_PREC_FP32 && prec != PT_PREC_FP64)
+    return fail(PT_ERR_UNSUPPORTED, "pt_lc_batch_noalloc runs PT_PREC_FP32 or PT_PREC_FP64");
+  pt_status st = validate_batch(batch, model, 0, prec);
+  if (st != PT_OK) return st;
+  if (batch->n_lc == 0 || batch->band_off[batch->n_lc] == batch->band_off[0]) return ok();
+  if (batch->n_flux > 0 && !flux) return fail(PT_ERR_ARG, "flux is NULL");
+  const int64_t n_lc = batch->n_lc, n_band = batch->band_off[batch->n_lc];
+  // the parts whose size does not depend on the tiling, checked before any HIP call
+  const NoAllocLayout base = noalloc_layout(n_lc, n_band, 0);
+  if (base.end > kNoAllocBytes || base.stage_end - base.t_start > kNoAllocStageBytes)
+    return fail(PT_ERR_ARG,
+                "batch too large for pt_lc_batch_noalloc: %lld light curves and %lld bands need %zu bytes of "
+                "scratch, the maximum is %zu",
+                (long long)n_lc, (long long)n_band, base.end, kNoAllocBytes);
+  if (fault_injected()) return fail(PT_ERR_HIP, "fault injected (PT_FAULT_INJECT=hip)");
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int dev = current_device();
+  if (dev < 0 || dev >= 16) return fail(PT_ERR_UNSUPPORTED, "device index outside 0..15");
+  NoAllocDevice& D = g_noalloc[dev];
+  if (!D.ready) {
+    // once per device, with that device current
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PT_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    PT_HIP(hipEventCreateWithFlags(&D.staged, hipEventDisableTiming));
+    D.ptr = (unsigned char*)p;
+    D.ready = true;
+  }
+  // launch shape: a tuned one for this batch shape if there is one, else the
+  // default; tiles grow until the tile list fits the staging area
+  int tile_e = 0, wg = 0;
+  auto tu = g_tuned.find(plan_key(batch, model, 0, prec));
+  if (tu != g_tuned.end()) {
+    tile_e = tu->second.tile_e;
+    wg = tu->second.workgroups;
+  } else {
+    tile_e = default_tile(batch);
+    const int kp = prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
+    wg = std::max(1, cu_count()) * std::max(1, batch_blocks_per_cu(kp, kModelMA) * 3 / 2);
+  }
+  int64_t n_tiles = count_tiles(batch, tile_e);
+  NoAllocLayout L = noalloc_layout(n_lc, n_band, n_tiles);
+  while ((L.end > kNoAllocBytes || L.stage_end - L.t_start > kNoAllocStageBytes) && tile_e < (1 << 20)) {
+    tile_e *= 2;
+    n_tiles = count_tiles(batch, tile_e);
+    L = noalloc_layout(n_lc, n_band, n_tiles);
+  }
+  if (L.end > kNoAllocBytes || L.stage_end - L.t_start > kNoAllocStageBytes)
+    return fail(PT_ERR_ARG, "batch too large for pt_lc_batch_noalloc: needs %zu bytes of scratch, the maximum is %zu",
+                L.end, kNoAllocBytes);
+  // the previous copy out of the staging area must be done before it is rewritten
+  if (g_noalloc_last_dev >= 0) PT_HIP(hipEventSynchronize(g_noalloc[g_noalloc_last_dev].staged));
+  // host mirror of [t_start, stage_end): offset x of scratch is h[x - t_start]
+  unsigned char* h = g_noalloc_stage;
+  memcpy(h + (L.t_start - L.t_start), batch->t_start, n_lc * 8);
+  memcpy(h + (L.t_count - L.t_start), batch->t_count, n_lc * 8);
+  memcpy(h + (L.nss - L.t_start), batch->nss, n_lc * 4);
+  memcpy(h + (L.band_off - L.t_start), batch->band_off, (n_lc + 1) * 4);
+  memcpy(h + (L.flux_off - L.t_start), batch->flux_off, n_lc * 8);
+  noalloc_tiles(batch, tile_e, reinterpret_cast<TileDesc*>(h + (L.tiles - L.t_start)), n_tiles);
+  hipStream_t s = (hipStream_t)stream;
+  PT_HIP(hipMemcpyAsync(D.ptr + L.t_start, g_noalloc_stage, L.stage_end - L.t_start, hipMemcpyHostToDevice, s));
+  PT_HIP(hipEventRecord(D.staged, s));
+  g_noalloc_last_dev = dev;
+  BatchArgs a;
+  memset(&a, 0, sizeof a);
+  a.t = batch->t; a.t0 = batch->t0; a.P = batch->P; a.aR = batch->aR; a.b = batch->b; a.e = batch->e;
+  a.w = batch->w; a.t_exp = batch->t_exp; a.k = batch->k; a.u = batch->u;
+  a.t_start = (const int64_t*)(D.ptr + L.t_start);
+  a.t_count = (const int64_t*)(D.ptr + L.t_count);
+  a.nss = (const int32_t*)(D.ptr + L.nss);
+  a.band_off = (const int32_t*)(D.ptr + L.band_off);
+  a.flux_off = (const int64_t*)(D.ptr + L.flux_off);
+  a.tiles = (const TileDesc*)(D.ptr + L.tiles);
+  a.n_tiles = n_tiles;
+  a.oc = (OrbitConst*)(D.ptr + L.oc);
+  a.ocf = (OrbitF*)(D.ptr + L.ocf);
+  a.bc = (BandConst*)(D.ptr + L.bc);
+  a.queue = (unsigned int*)D.ptr;   // reset by the prep kernel
+  a.flux = flux;
+  a.n_lc = (int32_t)n_lc;
+  a.n_band = (int32_t)n_band;
+  a.nldc = batch->nldc;
+  a.model = kModelMA;
+  PT_HIP(launch_batch(a, prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32, kModelMA, wg, s));
   return ok();
 }
 

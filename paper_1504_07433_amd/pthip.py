@@ -64,6 +64,7 @@ def _load():
         "pt_autotune": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int, vp, vp, C.c_char_p, C.c_size_t]),
         "pt_batch_launch_shape": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int,
                                        C.POINTER(i32), C.POINTER(i32)]),
+        "pt_lc_batch_noalloc": (st, [C.POINTER(PtBatch), C.c_int, C.c_int, vp, vp]),
         "pt_mlp_datagen": (st, [vp, i64, vp, vp]),
         "pt_mlp_forward": (st, [C.POINTER(PtMlp), vp, i64, vp, vp, vp]),
         "pt_mlp_backward": (st, [C.POINTER(PtMlp), vp, vp, vp, i64, C.POINTER(PtMlp), vp]),
@@ -85,7 +86,7 @@ def _load():
 lib = _load()
 SYMBOLS = [
     "pt_version", "pt_last_error", "pt_release", "pt_device_cu_count", "pt_orbit_z", "pt_ma_quad",
-    "pt_gimenez", "pt_ma_table_set", "pt_gimenez_zgrid_set", "pt_lc_batch", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
+    "pt_gimenez", "pt_ma_table_set", "pt_gimenez_zgrid_set", "pt_lc_batch", "pt_lc_batch_noalloc", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
     "pt_mlp_forward", "pt_mlp_backward", "pt_mlp_loss_grad", "pt_mlp_adam_step", "pt_surrogate_set",
     "pt_surrogate_trusted_fraction", "pt_surrogate_eval", "pt_mlp_infer",
 ]
@@ -197,6 +198,16 @@ def lc_batch(batch: DeviceBatch, model="ma", npol=50, prec="fp32", out=None):
         out = torch.empty(batch.n_flux, dtype=dtype, device=batch.dev["t"].device)
     s = batch.struct()
     _check(lib.pt_lc_batch(C.byref(s), MODEL[model], npol, PREC[prec], _ptr(out), _stream()))
+    return out
+
+
+def lc_batch_noalloc(batch: DeviceBatch, prec="fp32", out=None):
+    """pt_lc_batch_noalloc: quadratic Mandel-Agol, no device allocation by the library."""
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty(batch.n_flux, dtype=dtype, device=batch.dev["t"].device)
+    s = batch.struct()
+    _check(lib.pt_lc_batch_noalloc(C.byref(s), MODEL["ma"], PREC[prec], _ptr(out), _stream()))
     return out
 
 

@@ -130,3 +130,31 @@ def test_empty_batch_is_ok_without_device(pt):
     s = pt.PtBatch()
     s.n_lc, s.nldc = 0, 2
     assert pt.lib.pt_lc_batch(C.byref(s), 0, 50, 1, None, None) == pt.PT_OK
+
+
+def test_noalloc_host_checks(pt):
+    """pt_lc_batch_noalloc validates like pt_lc_batch, covers the quadratic
+    Mandel-Agol model in FP32/FP64 only, and rejects a batch whose scratch
+    exceeds its static array before any HIP call."""
+    L = pt.lib
+    s, keep = _batch_struct(pt)
+    assert L.pt_lc_batch_noalloc(C.byref(s), 1, 1, C.c_void_p(0x2000), None) == pt.PT_ERR_UNSUPPORTED
+    assert L.pt_lc_batch_noalloc(C.byref(s), 0, 2, C.c_void_p(0x2000), None) == pt.PT_ERR_UNSUPPORTED
+    assert L.pt_lc_batch_noalloc(C.byref(s), 0, 1, None, None) == pt.PT_ERR_ARG
+    assert "flux is NULL" in L.pt_last_error().decode()
+    s, keep = _batch_struct(pt, nss=np.array([0], np.int32))
+    assert L.pt_lc_batch_noalloc(C.byref(s), 0, 1, C.c_void_p(0x2000), None) == pt.PT_ERR_ARG
+    assert "nss" in L.pt_last_error().decode()
+    # 200,000 passbands need ~21 MB of band constants: over the 16 MiB array
+    nb = 200_000
+    s, keep = _batch_struct(pt, band_off=np.array([0, nb], np.int32), n_flux=nb * 1000)
+    st = L.pt_lc_batch_noalloc(C.byref(s), 0, 1, C.c_void_p(0x2000), None)
+    assert st == pt.PT_ERR_ARG
+    msg = L.pt_last_error().decode()
+    assert "too large for pt_lc_batch_noalloc" in msg and str(16 << 20) in msg
+
+
+def test_noalloc_empty_batch_is_ok_without_device(pt):
+    s = pt.PtBatch()
+    s.n_lc, s.nldc = 0, 2
+    assert pt.lib.pt_lc_batch_noalloc(C.byref(s), 0, 1, None, None) == pt.PT_OK
