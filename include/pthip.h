@@ -198,12 +198,36 @@ pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
 pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec,
                         const void* obs, const double* sigma, double* loglike, void* stream);
 
-/* Times the launch-shape candidates of pt_lc_batch for this batch (tile size,
- * resident waves per CU) with HIP events on `stream`, keeps the fastest for
- * the batch's shape, and writes a JSON report into report[report_len] (may be
- * NULL).  Runs the batch several times; synchronises the stream. */
+/* Picks the launch shape of pt_lc_batch for this batch shape by measurement
+ * (a project-side tuner; the paper has no counterpart).  Candidates: the
+ * default shape and every tile size in {64 .. 4096} exposures x requested
+ * waves per CU in {4, 6, 8, 12, 16, 24, 32}.  Each candidate is captured into
+ * a graph and replayed on `stream` as pt_lc_batch replays it: untimed replays
+ * first (more for the first candidate, which also brings the clocks up), then
+ * the median of seven replays timed with HIP events.  The fastest shape is
+ * kept for the batch shape (it can only be the default when nothing beats
+ * it) and used by later pt_lc_batch / pt_lc_batch_noalloc calls of that
+ * shape on any stream; a JSON report with every candidate's median, the
+ * default's and the best goes into report[report_len] (may be NULL).
+ * flux: as for pt_lc_batch (overwritten).  Synchronises the stream. */
 pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_prec prec,
                       void* flux, void* stream, char* report, size_t report_len);
+
+/* The tuned-shape cache on disk, as JSON lines, one object per batch shape:
+ *   {"key": "<gfx arch>|<batch shape>", "tile_exposures": T, "workgroups": W,
+ *    "cu": C, "ms": M, "default_ms": D}
+ * The key is the GPU architecture and the batch shape (model, precision,
+ * npol, sizes and hashes of the host shape arrays), so a file written on one
+ * GPU serves every GPU of the same architecture; workgroups scale with the
+ * compute-unit count when it differs from C.
+ * pt_tune_save writes every shape tuned or loaded so far (path is created or
+ * truncated).  pt_tune_load merges a file into the cache (plans made before
+ * take their tuned shape at once) and stores the number of entries read in
+ * *n_loaded (may be NULL).  Errors: PT_ERR_ARG for a NULL path, a file that
+ * cannot be opened, or a line that is not a tuned-shape object (nothing after
+ * it is read). */
+pt_status pt_tune_save(const char* path);
+pt_status pt_tune_load(const char* path, int32_t* n_loaded);
 
 /* Last launch shape used for a batch shape (-1 if none): tile exposures and
  * workgroups of the persistent grid. */
@@ -286,6 +310,16 @@ pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, d
 /* Fraction of trust-map cells (over c = z/(1+k) in [0,1), k in [k_lo, k_hi])
  * in which the exact model accepted the installed network (-1 on error). */
 double pt_surrogate_trusted_fraction(void);
+
+/* Point counters of the installed surrogate on this device: out[0] = points
+ * the batch kernels (PT_PREC_SURROGATE) took from the network, out[1] =
+ * in-transit points they evaluated with the exact functions instead (outside
+ * the trusted cells or inside the fallback band), each (subsample, passband)
+ * pair counted once, summed over every call since pt_surrogate_set or the
+ * last reset.  reset != 0 sets both to zero after reading.  Synchronous (a
+ * device-to-host copy; the caller orders it after the calls it counts).
+ * Errors: PT_ERR_ARG for NULL out, PT_ERR_UNSUPPORTED without a surrogate. */
+pt_status pt_surrogate_counters(uint64_t* out, int32_t reset);
 
 /* Raw outputs (alpha/k^2 units) of the installed network on its bf16-MFMA
  * inference path for float rows zk[n][2], out[n][3] float: no trust map and

@@ -1,0 +1,92 @@
+// batch_queue.h -- the work list of the persistent batch kernel: tiles (a
+// light curve's run of exposures), their order, the per-light-curve tile
+// lists of the likelihood reduction, and the pop protocol of the tile queue.
+// Plain host/device code without HIP calls, so that the host tests build it
+// with the system compiler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stdint.h>
+#include <vector>
+
+namespace pt {
+
+// The tile queue is split into kQueues sub-queues (tile q + i kQueues is the
+// i-th tile of sub-queue q), each with its own counter on its own 128-byte
+// line: one counter serialises its atomics at the memory side, and the pops
+// of all waves of the GPU otherwise meet on it.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;   // unsigned ints between counters
+constexpr int kWaveLanes = 64;
+
+// One unit of the persistent queue: exposures e0 .. e0+ne-1 of light curve lc.
+struct TileDesc {
+  int32_t lc;
+  int32_t e0;
+  int32_t ne;
+  int32_t pad;
+};
+
+// The next tile for a wave.  `pop(q)` returns the old value of sub-queue q's
+// counter and increments it (an atomic on the GPU, wave-uniform).  A wave
+// starts on sub-queue q0 and moves on when the one it is on runs dry; since
+// counters only grow, a sub-queue that ran dry stays dry, so after kQueues
+// dry pops every sub-queue is exhausted and the function returns false.
+// Between two calls the caller keeps q and dry.
+template <class Pop>
+__host__ __device__ __forceinline__ bool next_tile(int& q, int& dry, int64_t n_tiles, Pop pop, uint32_t* tile) {
+  for (;;) {
+    const unsigned int pos = pop(q);
+    const uint64_t t = (uint64_t)pos * kQueues + (uint64_t)q;
+    if (t < (uint64_t)n_tiles) {
+      *tile = (uint32_t)t;
+      return true;
+    }
+    if (++dry == kQueues) return false;
+    q = q + 1 == kQueues ? 0 : q + 1;
+  }
+}
+
+// Work estimate of a tile: wave iterations x subsamples x (bands + the orbit).
+inline double tile_work(int ne, int nss, int nb) {
+  return double((ne + kWaveLanes - 1) / kWaveLanes) * nss * (nb + 1.0);
+}
+
+// Tiles of a batch, longest first (ties in light-curve and exposure order, so
+// neighbouring tiles share cache lines), and per light curve the list of its
+// tile indices (CSR: lc_off[n_lc + 1], lc_tiles[n_tiles], in tile order).
+// Light curves without bands or exposures get no tile.
+struct TilePlan {
+  std::vector<TileDesc> tiles;
+  std::vector<int32_t> lc_off, lc_tiles;
+};
+
+inline void make_tile_plan(int32_t n_lc, const int64_t* t_count, const int32_t* nss, const int32_t* band_off,
+                           int tile_e, TilePlan* out) {
+  struct W {
+    double work;
+    TileDesc t;
+  };
+  std::vector<W> v;
+  for (int32_t lc = 0; lc < n_lc; ++lc) {
+    const int nb = band_off[lc + 1] - band_off[lc];
+    if (nb == 0) continue;
+    for (int64_t e0 = 0; e0 < t_count[lc]; e0 += tile_e) {
+      const int ne = (int)std::min<int64_t>(tile_e, t_count[lc] - e0);
+      v.push_back({tile_work(ne, nss[lc], nb), TileDesc{lc, (int32_t)e0, ne, 0}});
+    }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const W& a, const W& b) { return a.work > b.work; });
+  out->tiles.resize(v.size());
+  for (size_t i = 0; i < v.size(); ++i) out->tiles[i] = v[i].t;
+  out->lc_off.assign((size_t)n_lc + 1, 0);
+  out->lc_tiles.resize(v.size());
+  for (const TileDesc& t : out->tiles) out->lc_off[t.lc + 1]++;
+  for (int32_t i = 0; i < n_lc; ++i) out->lc_off[i + 1] += out->lc_off[i];
+  std::vector<int32_t> fill(out->lc_off.begin(), out->lc_off.end() - 1);
+  for (size_t j = 0; j < out->tiles.size(); ++j) out->lc_tiles[fill[out->tiles[j].lc]++] = (int32_t)j;
+}
+
+}  // namespace pt

@@ -37,6 +37,9 @@ struct MlpDev {
   float band;          // exact within |z - (1 +- k)| < band
   float k_lo, k_hi;    // trusted k range
   int32_t split;       // 1: hi/lo products, 0: bf16 hi only
+  // [0] points the batch kernels took from the network, [1] in-transit
+  // points they evaluated exactly in surrogate mode (pt_surrogate_counters)
+  unsigned long long* ctr;
 };
 
 __device__ __forceinline__ float silu(float x) { return x * __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }

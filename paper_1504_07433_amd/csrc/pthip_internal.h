@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "batch_queue.h"
 #include "transit_math.h"
 
 namespace pt {
@@ -22,13 +23,6 @@ struct BandConst {
   int32_t valid;        // k > 0 and finite weights
 };
 
-// One unit of the persistent queue: exposures e0 .. e0+ne-1 of light curve lc.
-struct TileDesc {
-  int32_t lc;
-  int32_t e0;
-  int32_t ne;
-  int32_t pad;
-};
 
 // kPrecSurrogateBf16: the surrogate with bf16-only products (no hi/lo split)
 enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2, kPrecSurrogateBf16 = 3 };
@@ -48,16 +42,9 @@ struct MaTable {
   int32_t nk, nz;
 };
 
-// The tile queue is split into kQueues sub-queues (tile q + i kQueues is the
-// i-th tile of sub-queue q), each with its own counter on its own 128-byte
-// line: one counter serialises its atomics at the memory side, and the pops
-// of all waves of the GPU otherwise meet on it.
-constexpr int kQueues = 8;
-constexpr int kQueueStride = 32;   // unsigned ints between counters
-
 // Subsamples whose z values a wave keeps in LDS at once.
 constexpr int kZChunk = 16;
-constexpr int kWave = 64;
+constexpr int kWave = kWaveLanes;
 constexpr int kBlock = 256;
 
 // Everything the persistent batch kernel reads.

@@ -549,14 +549,17 @@ __device__ __forceinline__ float ma_loss_surrogate(float z, const BandConst* __r
   const bool in = z >= 0.0f && z < bc->onepk;
   const bool tr = in && mlp_trusted(m, z, bc->kf);
   float loss = 0.0f;
-  if (__any(tr)) {
+  const uint64_t net = __ballot(tr), exact = __ballot(in && !tr);
+  if (net) {
     float y[3];
     mlp_eval_wave<SPLIT>(m, z, bc->kf, act, lane, y);
     if (tr) {
       const float k2 = bc->kf * bc->kf;
       loss = k2 * (bc->wf[0] * y[0] + bc->wf[1] * y[1] + bc->wf[2] * y[2]);
     }
+    if (lane == 0) atomicAdd(m->ctr, (unsigned long long)__popcll(net));
   }
+  if (exact && lane == 0) atomicAdd(m->ctr + 1, (unsigned long long)__popcll(exact));
   if (in && !tr) loss = ma_loss<float>(z, bc);
   return loss;
 }
@@ -779,17 +782,13 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
   // have: every wave ends after at most its tiles + kQueues pops.
   int q = (int)(blockIdx.x % kQueues);
   int dry = 0;
-  for (;;) {
+  auto pop = [&](int qq) {
     unsigned int pos = 0;
-    if (lane == 0) pos = atomicAdd(a.queue + q * kQueueStride, 1u);
-    pos = __builtin_amdgcn_readfirstlane(pos);
-    const uint64_t tile = (uint64_t)pos * kQueues + q;
-    if (tile >= (uint64_t)a.n_tiles) {
-      if (++dry == kQueues) break;
-      q = q + 1 == kQueues ? 0 : q + 1;
-      continue;
-    }
-    const unsigned int tid = (unsigned int)tile;
+    if (lane == 0) pos = atomicAdd(a.queue + qq * kQueueStride, 1u);
+    return (unsigned int)__builtin_amdgcn_readfirstlane(pos);
+  };
+  unsigned int tid = 0;
+  while (next_tile(q, dry, a.n_tiles, pop, &tid)) {
     const TileDesc td = load_uniform(a.tiles + tid);
     const int lc = td.lc;
     constexpr bool F32 = sizeof(T) == 4;

@@ -270,8 +270,9 @@ __global__ void k_pack_trust(const uint8_t* __restrict__ cells, MlpDev* __restri
   m->trust[w] = bits;
 }
 
-__global__ void k_set_params(MlpDev* m, float band, float k_lo, float k_hi, int split) {
-  m->band = band; m->k_lo = k_lo; m->k_hi = k_hi; m->split = split;
+__global__ void k_set_params(MlpDev* m, float band, float k_lo, float k_hi, int split, unsigned long long* ctr) {
+  m->band = band; m->k_lo = k_lo; m->k_hi = k_hi; m->split = split; m->ctr = ctr;
+  ctr[0] = 0ull; ctr[1] = 0ull;
 }
 
 // Surrogate values at (z, k) rows, with the exact fallback: out = alpha.
@@ -326,6 +327,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpDev* __restrict__ m,
 // Library-owned surrogate state for one device.
 struct SurrogateState {
   MlpDev* dev_ptr = nullptr;
+  unsigned long long* ctr = nullptr;   // the two point counters of MlpDev::ctr
   int dev = -1;
   bool ready = false;
   float band = 1e-3f, k_lo = 0.01f, k_hi = 0.3f;
@@ -350,6 +352,7 @@ void surrogate_release() {
       hipGetDevice(&cur);
       hipSetDevice(d);
       hipFree(g_sur[d].dev_ptr);
+      hipFree(g_sur[d].ctr);
       hipSetDevice(cur);
     }
     g_sur[d] = SurrogateState();
@@ -510,6 +513,7 @@ pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, d
   SurrogateState& st = g_sur[dev];
   hipStream_t s = (hipStream_t)stream;
   if (!st.dev_ptr) MLP_HIP(hipMalloc((void**)&st.dev_ptr, sizeof(MlpDev)));
+  if (!st.ctr) MLP_HIP(hipMalloc((void**)&st.ctr, 2 * sizeof(unsigned long long)));
   st.dev = dev;
   st.band = (float)fallback_band;
   st.k_lo = (float)k_lo;
@@ -517,7 +521,7 @@ pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, d
   const char* sp = getenv("PT_MLP_SPLIT");
   st.split = (sp && sp[0] == '0') ? 0 : 1;
   hipLaunchKernelGGL(k_mlp_pack, dim3(grid1(kH * kH)), dim3(256), 0, s, *w, st.dev_ptr);
-  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, s, st.dev_ptr, st.band, st.k_lo, st.k_hi, st.split);
+  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, s, st.dev_ptr, st.band, st.k_lo, st.k_hi, st.split, st.ctr);
   uint8_t* cells = nullptr;
   MLP_HIP(hipMallocAsync((void**)&cells, kTrustNC * kTrustNK, s));
   const size_t lds = 4 * kMlpLdsPerWave;
@@ -583,6 +587,23 @@ pt_status pt_mlp_infer(const float* zk, int64_t n, float* out, void* stream) {
     hipLaunchKernelGGL(k_mlp_infer<0>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
   }
   MLP_HIP(hipGetLastError());
+  return PT_OK;
+}
+
+pt_status pt_surrogate_counters(uint64_t* out, int32_t reset) {
+  if (!out) return set_error(PT_ERR_ARG, "out is NULL");
+  int dev = 0;
+  MLP_HIP(hipGetDevice(&dev));
+  if (!surrogate_device_ptr(dev)) return set_error(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
+  unsigned long long* c = g_sur[dev].ctr;
+  unsigned long long h[2] = {0ull, 0ull};
+  MLP_HIP(hipMemcpy(h, c, sizeof h, hipMemcpyDeviceToHost));
+  out[0] = h[0];
+  out[1] = h[1];
+  if (reset) {
+    const unsigned long long zero[2] = {0ull, 0ull};
+    MLP_HIP(hipMemcpy(c, zero, sizeof zero, hipMemcpyHostToDevice));
+  }
   return PT_OK;
 }
 

@@ -303,41 +303,20 @@ static pt_status build_tiles(Plan* p, int tile_e, TileSet** out) {
     *out = it->second.get();
     return PT_OK;
   }
-  struct W { double work; TileDesc t; };
-  std::vector<W> v;
-  for (int32_t lc = 0; lc < p->n_lc; ++lc) {
-    const int64_t c = p->t_count[lc];
-    const int nb = p->band_off[lc + 1] - p->band_off[lc];
-    if (nb == 0) continue;
-    for (int64_t e0 = 0; e0 < c; e0 += tile_e) {
-      const int ne = (int)std::min<int64_t>(tile_e, c - e0);
-      // wave iterations x subsamples x bands (+ the orbit per subsample)
-      const double work = double((ne + kWave - 1) / kWave) * p->nss[lc] * (nb + 1.0);
-      v.push_back({work, TileDesc{lc, (int32_t)e0, ne, 0}});
-    }
-  }
-  // longest first; equal work keeps light-curve order for cache locality
-  std::stable_sort(v.begin(), v.end(), [](const W& a, const W& b) { return a.work > b.work; });
-  std::vector<TileDesc> tiles(v.size());
-  for (size_t i = 0; i < v.size(); ++i) tiles[i] = v[i].t;
+  TilePlan tp;
+  make_tile_plan(p->n_lc, p->t_count.data(), p->nss.data(), p->band_off.data(), tile_e, &tp);
+  if (tp.tiles.size() > 0x7fffffffu) return fail(PT_ERR_ARG, "more than 2^31 tiles; use larger tiles");
   auto ts = std::make_unique<TileSet>();
-  ts->n_tiles = (int64_t)tiles.size();
-  PT_HIP(ts->tiles.ensure(std::max<size_t>(1, tiles.size()) * sizeof(TileDesc)));
-  if (!tiles.empty())
-    PT_HIP(hipMemcpy(ts->tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
-  if (tiles.size() > 0x7fffffffu) return fail(PT_ERR_ARG, "more than 2^31 tiles; use larger tiles");
-  std::vector<int32_t> off(p->n_lc + 1, 0), lst(tiles.size());
-  for (const TileDesc& t : tiles) off[t.lc + 1]++;
-  for (int32_t i = 0; i < p->n_lc; ++i) off[i + 1] += off[i];
-  {
-    std::vector<int32_t> fill(off.begin(), off.end() - 1);
-    for (size_t j = 0; j < tiles.size(); ++j) lst[fill[tiles[j].lc]++] = (int32_t)j;
-  }
-  PT_HIP(ts->lc_tile_off.ensure(off.size() * 4));
-  PT_HIP(ts->lc_tiles.ensure(std::max<size_t>(1, lst.size()) * 4));
-  PT_HIP(ts->partial.ensure(std::max<size_t>(1, tiles.size()) * 8));
-  PT_HIP(hipMemcpy(ts->lc_tile_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice));
-  if (!lst.empty()) PT_HIP(hipMemcpy(ts->lc_tiles.p, lst.data(), lst.size() * 4, hipMemcpyHostToDevice));
+  ts->n_tiles = (int64_t)tp.tiles.size();
+  PT_HIP(ts->tiles.ensure(std::max<size_t>(1, tp.tiles.size()) * sizeof(TileDesc)));
+  if (!tp.tiles.empty())
+    PT_HIP(hipMemcpy(ts->tiles.p, tp.tiles.data(), tp.tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
+  PT_HIP(ts->lc_tile_off.ensure(tp.lc_off.size() * 4));
+  PT_HIP(ts->lc_tiles.ensure(std::max<size_t>(1, tp.lc_tiles.size()) * 4));
+  PT_HIP(ts->partial.ensure(std::max<size_t>(1, tp.tiles.size()) * 8));
+  PT_HIP(hipMemcpy(ts->lc_tile_off.p, tp.lc_off.data(), tp.lc_off.size() * 4, hipMemcpyHostToDevice));
+  if (!tp.lc_tiles.empty())
+    PT_HIP(hipMemcpy(ts->lc_tiles.p, tp.lc_tiles.data(), tp.lc_tiles.size() * 4, hipMemcpyHostToDevice));
   *out = ts.get();
   p->tilesets[tile_e] = std::move(ts);
   return PT_OK;
@@ -362,7 +341,39 @@ static int default_tile(const pt_batch* b) {
   return te;
 }
 
-static std::map<std::string, LaunchShape> g_tuned;  // autotuned shapes by plan key
+// Autotuned launch shapes, by tune key: the GPU architecture and the batch
+// shape (the plan key without its device index), so that a cache written on
+// one GPU serves every GPU of the same kind.
+struct TunedShape {
+  LaunchShape shape;
+  int cu = 0;              // compute units of the GPU it was measured on
+  double ms = 0.0;         // median replay time of the chosen shape
+  double default_ms = 0.0; // the same for the default shape
+};
+static std::map<std::string, TunedShape> g_tuned;
+
+static std::string device_arch() {
+  hipDeviceProp_t prop;
+  const int dev = current_device();
+  if (dev < 0 || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a(prop.gcnArchName);
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);   // drop the feature suffix
+}
+
+static std::string tune_key(const std::string& shape_key) {
+  const size_t sp = shape_key.find(' ');
+  return device_arch() + "|" + (sp == std::string::npos ? shape_key : shape_key.substr(sp + 1));
+}
+
+// A tuned shape for this GPU: the workgroup count scales with its compute units.
+static LaunchShape tuned_for_device(const TunedShape& t) {
+  LaunchShape s = t.shape;
+  const int cu = cu_count();
+  if (t.cu > 0 && cu > 0 && cu != t.cu)
+    s.workgroups = std::max(1, (int)((int64_t)s.workgroups * cu / t.cu));
+  return s;
+}
 
 // A plan owns device scratch that every call rewrites (queue counters, orbit
 // and band constants, tables), so calls on different streams get plans of
@@ -372,6 +383,18 @@ static std::string stream_key(const std::string& shape_key, hipStream_t s) {
   char buf[32];
   snprintf(buf, sizeof buf, "s%llx", (unsigned long long)(uintptr_t)s);
   return shape_key + buf;
+}
+
+// The launch shape used when no tuned one is known: tiles from default_tile,
+// and since the kernel is persistent, what the compute units hold at once
+// plus half as many again (measured 2-3 % faster on MI355X than exactly the
+// resident count).
+static pt_status default_shape(const pt_batch* b, const Plan* p, LaunchShape* out) {
+  out->tile_e = default_tile(b);
+  if (prepare_batch_kernels() != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes");
+  const int resident = batch_blocks_per_cu(kernel_prec(p), p->model);
+  out->workgroups = std::max(1, cu_count()) * std::max(1, resident * 3 / 2);
+  return PT_OK;
 }
 
 static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_prec prec, hipStream_t stream,
@@ -425,18 +448,13 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
     PT_HIP(p->gtab64.ensure(nb * (b->nldc + 1) * gim_row(npol) * sizeof(double)));   // Jacobi rows
     PT_HIP(p->gtab.ensure(nb * (size_t)gim_band_stride(npol) * es));                  // folded rows
   }
-  auto tu = g_tuned.find(shape_key);
+  auto tu = g_tuned.find(tune_key(shape_key));
   if (tu != g_tuned.end()) {
-    p->shape = tu->second;
+    p->shape = tuned_for_device(tu->second);
     p->tuned = true;
   } else {
-    p->shape.tile_e = default_tile(b);
-    // The kernel is persistent: launch what the compute units hold at once,
-    // plus half as many again (measured 2-3 % faster on MI355X than exactly
-    // the resident count, the autotuner's usual choice).
-    if (prepare_batch_kernels() != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes");
-    const int resident = batch_blocks_per_cu(kernel_prec(p.get()), p->model);
-    p->shape.workgroups = std::max(1, cu_count()) * std::max(1, resident * 3 / 2);
+    pt_status ds = default_shape(b, p.get(), &p->shape);
+    if (ds != PT_OK) return ds;
   }
   PT_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
   *out = p.get();
@@ -621,9 +639,7 @@ static void noalloc_tiles(const pt_batch* b, int tile_e, TileDesc* out, int64_t 
     for (int64_t e0 = 0; e0 < b->t_count[lc]; e0 += tile_e)
       out[j++] = TileDesc{lc, (int32_t)e0, (int32_t)std::min<int64_t>(tile_e, b->t_count[lc] - e0), 0};
   }
-  auto work = [b](const TileDesc& t) {
-    return double((t.ne + kWave - 1) / kWave) * b->nss[t.lc] * (b->band_off[t.lc + 1] - b->band_off[t.lc] + 1.0);
-  };
+  auto work = [b](const TileDesc& t) { return tile_work(t.ne, b->nss[t.lc], b->band_off[t.lc + 1] - b->band_off[t.lc]); };
   std::sort(out, out + n_tiles, [&](const TileDesc& x, const TileDesc& y) {
     const double wx = work(x), wy = work(y);
     if (wx != wy) return wx > wy;
@@ -834,68 +850,183 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   if (st != PT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const int cu = std::max(1, cu_count());
-  const int tiles[] = {64, 128, 256, 512, 1024, 2048};
-  const int wpc[] = {4, 8, 12, 16, 24};     // resident waves per CU requested
-  hipEvent_t e0, e1;
-  PT_HIP(hipEventCreate(&e0));
-  PT_HIP(hipEventCreate(&e1));
-  std::string rep = "{\"candidates\": [";
-  float best = 1e30f;
-  LaunchShape best_shape = p->shape;
   const int prec_k = kernel_prec(p);
   {
     hipError_t pe = prepare_batch_kernels();
     if (pe != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes: %s", hipGetErrorString(pe));
   }
+  LaunchShape def;
+  st = default_shape(batch, p, &def);
+  if (st != PT_OK) return st;
+  // candidates: the default shape first, then tile sizes x requested waves per CU
+  std::vector<LaunchShape> cand{def};
+  const int tiles[] = {64, 128, 256, 512, 1024, 2048, 4096};
+  const int wpc[] = {4, 6, 8, 12, 16, 24, 32};
+  for (int te : tiles)
+    for (int w : wpc) {
+      LaunchShape c;
+      c.tile_e = te;
+      c.workgroups = cu * w / (kBlock / kWave);
+      if (c.workgroups >= 1 && !(c.tile_e == def.tile_e && c.workgroups == def.workgroups)) cand.push_back(c);
+    }
+  constexpr int kWarm = 3, kTimed = 7;
+  hipEvent_t ev[kTimed + 1];
+  for (auto& e : ev) PT_HIP(hipEventCreate(&e));
+  std::string rep = "{\"candidates\": [";
+  double best = 1e30, def_ms = 0.0;
+  LaunchShape best_shape = def;
   bool first = true;
-  for (int te : tiles) {
+  // Each candidate is captured into a graph and replayed as pt_lc_batch
+  // replays it: a few untimed replays, then the median of the timed ones.
+  // The first candidate's warm-up replays also bring the clocks up.
+  for (size_t ci = 0; ci < cand.size() && st == PT_OK; ++ci) {
+    const LaunchShape& c = cand[ci];
     BatchArgs a;
-    st = fill_args(batch, p, te, flux, &a);
+    st = fill_args(batch, p, c.tile_e, flux, &a);
     if (st != PT_OK) break;
     if (a.n_tiles == 0) continue;
-    for (int w : wpc) {
-      const int wg = cu * w / (kBlock / kWave);
-      if (wg < 1) continue;
-      if ((int64_t)wg * (kBlock / kWave) > 4 * a.n_tiles && w > 4) continue;  // mostly idle waves
-      float ms_best = 1e30f;
-      for (int rep_i = 0; rep_i < 3; ++rep_i) {
-        hipEventRecord(e0, s);
-        hipError_t le = launch_batch(a, prec_k, p->model, wg, s);
-        hipEventRecord(e1, s);
-        if (le != hipSuccess) { st = fail(PT_ERR_HIP, "autotune launch: %s", hipGetErrorString(le)); break; }
-        if (hipEventSynchronize(e1) != hipSuccess) { st = fail(PT_ERR_HIP, "autotune sync"); break; }
-        float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
-        ms_best = std::min(ms_best, ms);
-      }
-      if (st != PT_OK) break;
-      char buf[160];
-      snprintf(buf, sizeof buf, "%s{\"tile_exposures\": %d, \"waves_per_cu\": %d, \"workgroups\": %d, \"ms\": %.5f}",
-               first ? "" : ", ", te, w, wg, ms_best);
-      first = false;
-      rep += buf;
-      if (ms_best < best) {
-        best = ms_best;
-        best_shape.tile_e = te;
-        best_shape.workgroups = wg;
-      }
+    if (ci > 0 && (int64_t)c.workgroups * (kBlock / kWave) > 4 * a.n_tiles) continue;   // mostly idle waves
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    PT_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batch(a, prec_k, p->model, c.workgroups, p->capture_stream);
+    hipError_t ce = hipStreamEndCapture(p->capture_stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      st = fail(PT_ERR_HIP, "autotune capture: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+      break;
     }
-    if (st != PT_OK) break;
+    hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) { st = fail(PT_ERR_HIP, "autotune instantiate: %s", hipGetErrorString(ie)); break; }
+    const int warm = ci == 0 ? 4 * kWarm : kWarm;
+    hipError_t re = hipSuccess;
+    for (int i = 0; i < warm && re == hipSuccess; ++i) re = hipGraphLaunch(ge, s);
+    for (int i = 0; i < kTimed && re == hipSuccess; ++i) {
+      re = hipEventRecord(ev[i], s);
+      if (re == hipSuccess) re = hipGraphLaunch(ge, s);
+    }
+    if (re == hipSuccess) re = hipEventRecord(ev[kTimed], s);
+    if (re == hipSuccess) re = hipEventSynchronize(ev[kTimed]);
+    hipGraphExecDestroy(ge);
+    if (re != hipSuccess) { st = fail(PT_ERR_HIP, "autotune replay: %s", hipGetErrorString(re)); break; }
+    std::vector<double> ms(kTimed);
+    for (int i = 0; i < kTimed; ++i) {
+      float t = 0.0f;
+      hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      ms[i] = t;
+    }
+    std::sort(ms.begin(), ms.end());
+    const double med = ms[kTimed / 2];
+    if (ci == 0) def_ms = med;
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "%s{\"tile_exposures\": %d, \"workgroups\": %d, \"waves_per_cu\": %.2f, \"ms\": %.5f%s}",
+             first ? "" : ", ", c.tile_e, c.workgroups, (double)c.workgroups * (kBlock / kWave) / cu, med,
+             ci == 0 ? ", \"default\": true" : "");
+    first = false;
+    rep += buf;
+    if (med < best) {
+      best = med;
+      best_shape = c;
+    }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  for (auto& e : ev) hipEventDestroy(e);
   if (st != PT_OK) return st;
   p->shape = best_shape;
   p->tuned = true;
-  g_tuned[key] = best_shape;
-  char buf[160];
-  snprintf(buf, sizeof buf, "], \"best\": {\"tile_exposures\": %d, \"workgroups\": %d, \"ms\": %.5f}}",
-           best_shape.tile_e, best_shape.workgroups, best);
+  TunedShape t;
+  t.shape = best_shape;
+  t.cu = cu;
+  t.ms = best;
+  t.default_ms = def_ms;
+  g_tuned[tune_key(key)] = t;
+  char buf[240];
+  snprintf(buf, sizeof buf,
+           "], \"best\": {\"tile_exposures\": %d, \"workgroups\": %d, \"ms\": %.5f}, \"default_ms\": %.5f}",
+           best_shape.tile_e, best_shape.workgroups, best, def_ms);
   rep += buf;
   if (report && report_len > 0) {
     strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
+  return ok();
+}
+
+// The tuned-shape cache as JSON lines, one object per batch shape:
+//   {"key": "<arch>|<shape>", "tile_exposures": T, "workgroups": W, "cu": C, "ms": M, "default_ms": D}
+pt_status pt_tune_save(const char* path) {
+  if (!path) return fail(PT_ERR_ARG, "path is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(PT_ERR_ARG, "cannot write %s", path);
+  for (const auto& kv : g_tuned)
+    fprintf(f, "{\"key\": \"%s\", \"tile_exposures\": %d, \"workgroups\": %d, \"cu\": %d, \"ms\": %.5f, "
+               "\"default_ms\": %.5f}\n",
+            kv.first.c_str(), kv.second.shape.tile_e, kv.second.shape.workgroups, kv.second.cu, kv.second.ms,
+            kv.second.default_ms);
+  const bool bad = ferror(f) != 0;
+  if (fclose(f) != 0 || bad) return fail(PT_ERR_ARG, "write error on %s", path);
+  return ok();
+}
+
+static bool json_int(const char* line, const char* name, long long* v) {
+  const char* q = strstr(line, name);
+  if (!q) return false;
+  q = strchr(q + strlen(name), ':');
+  return q && sscanf(q + 1, "%lld", v) == 1;
+}
+
+static bool json_num(const char* line, const char* name, double* v) {
+  const char* q = strstr(line, name);
+  if (!q) return false;
+  q = strchr(q + strlen(name), ':');
+  return q && sscanf(q + 1, "%lf", v) == 1;
+}
+
+pt_status pt_tune_load(const char* path, int32_t* n_loaded) {
+  if (!path) return fail(PT_ERR_ARG, "path is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(PT_ERR_ARG, "cannot read %s", path);
+  char line[4096];
+  int n = 0, lineno = 0;
+  pt_status st = PT_OK;
+  while (fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (line[0] == '\n' || line[0] == 0) continue;
+    const char* k = strstr(line, "\"key\"");
+    const char* k0 = k ? strchr(k + 5, '"') : nullptr;
+    const char* k1 = k0 ? strchr(k0 + 1, '"') : nullptr;
+    long long te = 0, wg = 0, cu = 0;
+    double ms = 0.0, dms = 0.0;
+    if (!k1 || !json_int(line, "\"tile_exposures\"", &te) || !json_int(line, "\"workgroups\"", &wg) ||
+        !json_int(line, "\"cu\"", &cu) || te < 1 || te > (1 << 20) || wg < 1 || wg > (1 << 24)) {
+      st = fail(PT_ERR_ARG, "%s:%d: not a tuned-shape line", path, lineno);
+      break;
+    }
+    json_num(line, "\"ms\"", &ms);
+    json_num(line, "\"default_ms\"", &dms);
+    TunedShape t;
+    t.shape.tile_e = (int)te;
+    t.shape.workgroups = (int)wg;
+    t.cu = (int)cu;
+    t.ms = ms;
+    t.default_ms = dms;
+    g_tuned[std::string(k0 + 1, k1)] = t;
+    ++n;
+  }
+  fclose(f);
+  if (st != PT_OK) return st;
+  // plans made before the load take their tuned shape now
+  for (auto& kv : g_plans) {
+    auto it = g_tuned.find(tune_key(kv.second->shape_key));
+    if (it != g_tuned.end() && !kv.second->tuned) {
+      kv.second->shape = tuned_for_device(it->second);
+      kv.second->tuned = true;
+    }
+  }
+  if (n_loaded) *n_loaded = n;
   return ok();
 }
 
@@ -934,10 +1065,11 @@ pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec pre
   // launch shape: a tuned one for this batch shape if there is one, else the
   // default; tiles grow until the tile list fits the staging area
   int tile_e = 0, wg = 0;
-  auto tu = g_tuned.find(plan_key(batch, model, 0, prec));
+  auto tu = g_tuned.find(tune_key(plan_key(batch, model, 0, prec)));
   if (tu != g_tuned.end()) {
-    tile_e = tu->second.tile_e;
-    wg = tu->second.workgroups;
+    const LaunchShape ts = tuned_for_device(tu->second);
+    tile_e = ts.tile_e;
+    wg = ts.workgroups;
   } else {
     tile_e = default_tile(batch);
     const int kp = prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;

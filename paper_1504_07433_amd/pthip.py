@@ -65,6 +65,8 @@ def _load():
         "pt_batch_launch_shape": (st, [C.POINTER(PtBatch), C.c_int, i32, C.c_int,
                                        C.POINTER(i32), C.POINTER(i32)]),
         "pt_lc_batch_noalloc": (st, [C.POINTER(PtBatch), C.c_int, C.c_int, vp, vp]),
+        "pt_tune_save": (st, [C.c_char_p]),
+        "pt_tune_load": (st, [C.c_char_p, C.POINTER(i32)]),
         "pt_mlp_datagen": (st, [vp, i64, vp, vp]),
         "pt_mlp_forward": (st, [C.POINTER(PtMlp), vp, i64, vp, vp, vp]),
         "pt_mlp_backward": (st, [C.POINTER(PtMlp), vp, vp, vp, i64, C.POINTER(PtMlp), vp]),
@@ -74,6 +76,7 @@ def _load():
         "pt_surrogate_set": (st, [C.POINTER(PtMlp), d, d, d, vp]),
         "pt_surrogate_trusted_fraction": (d, []),
         "pt_surrogate_eval": (st, [vp, i64, vp, vp]),
+        "pt_surrogate_counters": (st, [C.POINTER(C.c_uint64), i32]),
         "pt_mlp_infer": (st, [vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -86,9 +89,10 @@ def _load():
 lib = _load()
 SYMBOLS = [
     "pt_version", "pt_last_error", "pt_release", "pt_device_cu_count", "pt_orbit_z", "pt_ma_quad",
-    "pt_gimenez", "pt_ma_table_set", "pt_gimenez_zgrid_set", "pt_lc_batch", "pt_lc_batch_noalloc", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape", "pt_mlp_datagen",
+    "pt_gimenez", "pt_ma_table_set", "pt_gimenez_zgrid_set", "pt_lc_batch", "pt_lc_batch_noalloc", "pt_lc_loglike", "pt_autotune", "pt_batch_launch_shape",
+    "pt_tune_save", "pt_tune_load", "pt_mlp_datagen",
     "pt_mlp_forward", "pt_mlp_backward", "pt_mlp_loss_grad", "pt_mlp_adam_step", "pt_surrogate_set",
-    "pt_surrogate_trusted_fraction", "pt_surrogate_eval", "pt_mlp_infer",
+    "pt_surrogate_trusted_fraction", "pt_surrogate_eval", "pt_surrogate_counters", "pt_mlp_infer",
 ]
 
 
@@ -243,6 +247,19 @@ def autotune(batch: DeviceBatch, model="ma", npol=50, prec="fp32", out=None):
     return json.loads(buf.value.decode())
 
 
+def tune_save(path):
+    """Writes every tuned launch shape to a JSON-lines file."""
+    _check(lib.pt_tune_save(os.fsencode(path)))
+
+
+def tune_load(path) -> int:
+    """Merges a tuned-shape file into the library's cache; returns the number
+    of entries read."""
+    n = C.c_int32(0)
+    _check(lib.pt_tune_load(os.fsencode(path), C.byref(n)))
+    return n.value
+
+
 def launch_shape(batch: DeviceBatch, model="ma", npol=50, prec="fp32"):
     s = batch.struct()
     te, wg = C.c_int32(), C.c_int32()
@@ -310,6 +327,16 @@ def surrogate_eval(zk):
     out = torch.empty((zk.shape[0], 3), dtype=torch.float64, device=zk.device)
     _check(lib.pt_surrogate_eval(_ptr(zk), zk.shape[0], _ptr(out), _stream()))
     return out
+
+
+def surrogate_counters(reset=False):
+    """(points taken from the network, in-transit points evaluated exactly) by
+    the surrogate batch path since installation or the last reset; waits for
+    the device."""
+    torch.cuda.synchronize()
+    out = (C.c_uint64 * 2)()
+    _check(lib.pt_surrogate_counters(out, 1 if reset else 0))
+    return int(out[0]), int(out[1])
 
 
 def mlp_infer(zk32):

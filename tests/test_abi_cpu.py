@@ -158,3 +158,28 @@ def test_noalloc_empty_batch_is_ok_without_device(pt):
     s = pt.PtBatch()
     s.n_lc, s.nldc = 0, 2
     assert pt.lib.pt_lc_batch_noalloc(C.byref(s), 0, 1, None, None) == pt.PT_OK
+
+
+def test_tune_cache_round_trip_and_errors(pt, tmp_path):
+    """The tuned-shape file: lines are read back as written, a malformed line
+    is refused with its line number, and a missing file is an error."""
+    good = tmp_path / "tune.jsonl"
+    good.write_text(
+        '{"key": "gfx950|m0 p0 q1 n2 l2 t10 f20|00:8;", "tile_exposures": 512, "workgroups": 1536, '
+        '"cu": 256, "ms": 1.5, "default_ms": 1.6}\n'
+        '{"key": "gfx950|m1 p50 q0 n3 l2 t10 f20|01:8;", "tile_exposures": 64, "workgroups": 256, '
+        '"cu": 256, "ms": 0.25, "default_ms": 0.25}\n')
+    assert pt.tune_load(str(good)) == 2
+    out = tmp_path / "out.jsonl"
+    pt.tune_save(str(out))
+    lines = out.read_text().splitlines()
+    keys = {ln.split('"key": "')[1].split('"')[0]: ln for ln in lines}
+    assert "gfx950|m0 p0 q1 n2 l2 t10 f20|00:8;" in keys
+    assert '"tile_exposures": 64, "workgroups": 256' in keys["gfx950|m1 p50 q0 n3 l2 t10 f20|01:8;"]
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text(good.read_text().splitlines()[0] + "\n" + '{"key": "x", "tile_exposures": 0}\n')
+    with pytest.raises(pt.PthipError, match="bad.jsonl:2"):
+        pt.tune_load(str(bad))
+    with pytest.raises(pt.PthipError, match="cannot read"):
+        pt.tune_load(str(tmp_path / "missing.jsonl"))
+    pt.release()

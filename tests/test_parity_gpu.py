@@ -354,17 +354,29 @@ def test_batch_two_streams_same_shape(pt, O):
         assert np.abs(g2.cpu().numpy() - ref2).max() <= TOL32
 
 
-def test_autotune_keeps_results(pt):
+def test_autotune_keeps_results(pt, tmp_path):
+    """The tuner times the default shape first and keeps a shape no slower
+    than it; the tuned shape changes no result, and a cache file written by
+    pt_tune_save gives a fresh library state the same shape."""
     from paper_1504_07433_amd import workloads as W
     b = W.config4(n_lc=40, n_min=100, n_max=5000)
     db = pt.DeviceBatch(b)
     before = pt.lc_batch(db, "ma", prec="fp32").cpu().numpy()
     rep = pt.autotune(db, "ma", prec="fp32")
-    assert rep["best"]["ms"] > 0 and len(rep["candidates"]) > 3
+    cands = rep["candidates"]
+    assert cands[0].get("default") and len(cands) >= 5
+    assert 0 < rep["best"]["ms"] <= rep["default_ms"] == cands[0]["ms"]
     te, wg = pt.launch_shape(db, "ma", prec="fp32")
     assert te == rep["best"]["tile_exposures"] and wg == rep["best"]["workgroups"]
     after = pt.lc_batch(db, "ma", prec="fp32").cpu().numpy()
     assert np.array_equal(before, after)
+    path = str(tmp_path / "tune.jsonl")
+    pt.tune_save(path)
+    pt.release()
+    assert pt.tune_load(path) >= 1
+    again = pt.lc_batch(db, "ma", prec="fp32").cpu().numpy()
+    assert pt.launch_shape(db, "ma", prec="fp32") == (te, wg)
+    assert np.array_equal(before, again)
 
 
 # --- full sizes, in the benchmark's launch configuration, on sampled outputs ----
