@@ -3,11 +3,13 @@
 TEST INFRASTRUCTURE ONLY (like the rest of oracle/): used to check the HIP
 forward, loss and backward kernels.  Written from the definitions: a
 2-128-128-128-3 multilayer perceptron with SiLU activations,
-silu(x) = x / (1 + exp(-x)), inputs x = (2 z/(1+k) - 1, (k - 0.155)/0.145),
-outputs compared with alpha/k^2 where alpha are the three limb-darkening-
-factored Mandel & Agol functions, and the weighted squared error
-mean over rows and outputs of w(k) (y - alpha/k^2)^2, w(k) = (k/0.3)^4 + 1e-3.
-Weights are row-major [out][in] as in the C ABI.
+silu(x) = x / (1 + exp(-x)), over the inside of the stellar disc, inputs
+x = (2 sqrt(1 - z/(1-k)) - 1, (k - 0.155)/0.145), outputs compared with
+  t0 = lambda_e/k^2, t1 = (alpha_1/k^2 - sqrt(1 - z^2))/k^2, t2 = eta_d/k^2,
+alpha_1 = lambda_d + 2/3 Theta(k - z) (the three limb-darkening-factored
+Mandel & Agol functions, Sect. 2.2.1), and the weighted squared error, mean
+over rows and outputs of w(k) c_j (y_j - t_j)^2 with w(k) = (k/0.3)^8 + 1e-5
+and c = (0.1, 1, 0.1).  Weights are row-major [out][in] as in the C ABI.
 """
 from __future__ import annotations
 
@@ -30,7 +32,20 @@ def init_weights(seed=0):
 
 def features(zk):
     z, k = zk[:, 0], zk[:, 1]
-    return np.stack([2 * z / (1 + k) - 1, (k - 0.155) / 0.145], 1)
+    return np.stack([2 * np.sqrt(np.maximum(0.0, 1 - z / (1 - k))) - 1, (k - 0.155) / 0.145], 1)
+
+
+def targets(zk, alpha):
+    """The three training targets of rows (z, k) with functions alpha."""
+    z, k = zk[:, 0], zk[:, 1]
+    k2 = k * k
+    return np.stack([alpha[:, 0] / k2, (alpha[:, 1] / k2 - np.sqrt(np.maximum(0.0, 1 - z * z))) / k2,
+                     alpha[:, 2] / k2], 1)
+
+
+def row_weights(zk):
+    k = zk[:, 1]
+    return ((k / 0.3) ** 8 + 1e-5)[:, None] * np.array([0.1, 1.0, 0.1])[None, :]
 
 
 def silu(x):
@@ -50,20 +65,14 @@ def forward(w, zk):
 
 def loss(w, zk, alpha):
     y, _ = forward(w, zk)
-    k = zk[:, 1]
-    t = alpha / (k * k)[:, None]
-    wt = (k / 0.3) ** 4 + 1e-3
-    return float(np.mean(wt[:, None] * (y - t) ** 2))
+    return float(np.mean(row_weights(zk) * (y - targets(zk, alpha)) ** 2))
 
 
 def grad(w, zk, alpha):
     """Analytic gradient of loss() by the chain rule, layer by layer."""
     y, pres = forward(w, zk)
-    k = zk[:, 1]
-    n = len(k)
-    t = alpha / (k * k)[:, None]
-    wt = (k / 0.3) ** 4 + 1e-3
-    dy = 2 * wt[:, None] * (y - t) / (3 * n)
+    n = len(zk)
+    dy = 2 * row_weights(zk) * (y - targets(zk, alpha)) / (3 * n)
     g = {}
     hs = [features(zk)] + [silu(p) for p in pres]
     g["W4"] = dy.T @ hs[3]

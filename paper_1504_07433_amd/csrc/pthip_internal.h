@@ -47,6 +47,17 @@ constexpr int kZChunk = 16;
 constexpr int kWave = kWaveLanes;
 constexpr int kBlock = 256;
 
+// A (subsample, exposure, band) point the surrogate path leaves to the
+// network: its z, band and flux element; the network pass subtracts the
+// point's loss / nss from that element.
+struct SurEntry {
+  float z;
+  int32_t band;
+  uint64_t idx_nss;     // flux index (low 48 bits) | nss << 48
+};
+constexpr int kSurNssShift = 48;
+constexpr int64_t kSurListMax = int64_t(1) << 26;   // entries per call (1 GiB)
+
 // Everything the persistent batch kernel reads.
 struct BatchArgs {
   const double* t;
@@ -84,6 +95,10 @@ struct BatchArgs {
   int32_t model;
   // surrogate
   const void* mlp;      // device MlpDev (bf16 weights) or null
+  SurEntry* sur_list;   // points left to the network [sur_cap]
+  unsigned int* sur_count;  // entries written (reset by the prep kernel)
+  int64_t sur_cap;      // 0: no list, every point takes the float path
+  int32_t sur_grid;     // workgroups of the network pass
   // fused likelihood (obs == null: write flux)
   const void* obs;      // observed flux, same layout and type as flux
   const double* sigma;  // [n_lc] white-noise sigma
@@ -98,6 +113,13 @@ struct BatchArgs {
   float* ztab;          // [n_band][zin + zlimb] loss at the z nodes (kModelGimenezZInterp)
   int32_t zin, zlimb;
 };
+
+// Makes this wave's LDS writes visible to its other lanes before they read.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // Read-only data at a wave-uniform address, read through the constant
 // address space so that the compiler issues scalar loads.  Only for data no

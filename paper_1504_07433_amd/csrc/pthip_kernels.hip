@@ -407,6 +407,7 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
 
 __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
   if (blockIdx.x == 0 && threadIdx.x < kQueues) a.queue[threadIdx.x * kQueueStride] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == kQueues && a.sur_count) *a.sur_count = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_band; i += stride)
     a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
@@ -540,28 +541,74 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
   return se + Num<T>::sqrt(om) * so;
 }
 
-// Surrogate: lanes whose (z, k) fall in a trusted cell take the network's
-// functions, the others the float path; the network runs for the whole
-// wave (MFMA) whenever any lane needs it.
-template <int SPLIT>
-__device__ __forceinline__ float ma_loss_surrogate(float z, const BandConst* __restrict__ bc,
-                                                   const MlpDev* __restrict__ m, __bf16* act, int lane) {
-  const bool in = z >= 0.0f && z < bc->onepk;
-  const bool tr = in && mlp_trusted(m, z, bc->kf);
-  float loss = 0.0f;
-  const uint64_t net = __ballot(tr), exact = __ballot(in && !tr);
-  if (net) {
-    float y[3];
-    mlp_eval_wave<SPLIT>(m, z, bc->kf, act, lane, y);
-    if (tr) {
-      const float k2 = bc->kf * bc->kf;
-      loss = k2 * (bc->wf[0] * y[0] + bc->wf[1] * y[1] + bc->wf[2] * y[2]);
+// Surrogate path, first pass: a point inside the stellar disc whose
+// error-map cell keeps the band's flux error within tolerance is left to the
+// network (appended to the list, its loss added by k_sur_net); every other
+// in-transit point takes the float path here.  The wave reserves list slots
+// with one atomic; a point that finds the list full takes the float path.
+// Returns the loss summed over the subsamples of the chunk, without the
+// network's points.
+__device__ __forceinline__ float sur_loss_sum(const float* zb, int ns, int lane, const BandConst* __restrict__ bc,
+                                              int bnd, const BatchArgs& a, uint64_t idx_nss, bool act_lane) {
+  const MlpDev* __restrict__ m = reinterpret_cast<const MlpDev*>(a.mlp);
+  const float w1 = fabsf(bc->wf[1]);
+  float acc = 0.0f;
+  for (int s = 0; s < ns; ++s) {
+    const float z = zb[s * kWave + lane];
+    const bool in = act_lane && z >= 0.0f && z < bc->onepk;
+    const int cell = in ? mlp_cell(m, z, bc->kf) : -1;
+    bool net = a.sur_cap > 0 && cell >= 0 && w1 * m->err[cell] <= kSurrogateFluxTol;
+    const uint64_t netm = __ballot(net);
+    if (netm) {
+      unsigned int base = 0;
+      if (lane == 0) base = atomicAdd(a.sur_count, (unsigned int)__popcll(netm));
+      base = __builtin_amdgcn_readfirstlane(base);
+      const uint64_t slot = (uint64_t)base + (uint64_t)__popcll(netm & ((1ull << lane) - 1ull));
+      if (net) {
+        if (slot < (uint64_t)a.sur_cap) a.sur_list[slot] = SurEntry{z, bnd, idx_nss};
+        else net = false;
+      }
     }
-    if (lane == 0) atomicAdd(m->ctr, (unsigned long long)__popcll(net));
+    const bool ex = in && !net;
+    const uint64_t exm = __ballot(ex);
+    if (exm && lane == 0) atomicAdd(m->ctr + 1, (unsigned long long)__popcll(exm));
+    if (ex) acc += ma_loss<float>(z, bc);
   }
-  if (exact && lane == 0) atomicAdd(m->ctr + 1, (unsigned long long)__popcll(exact));
-  if (in && !tr) loss = ma_loss<float>(z, bc);
-  return loss;
+  return acc;
+}
+
+// Surrogate path, second pass: the network over the listed points, 64 per
+// wave (every lane a network point), the loss from alpha_1 of the network
+// and the polynomials lambda_e = k^2, eta_d = k^2 (k^2 + 2 z^2)/2, taken off
+// the point's flux element (1/nss of it; elements with several listed
+// subsamples receive them in no fixed order).  Waves stride over the list;
+// the list length is read from the device.
+template <int SPLIT>
+__global__ __launch_bounds__(256) void k_sur_net(BatchArgs a) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const MlpDev* __restrict__ m = reinterpret_cast<const MlpDev*>(a.mlp);
+  float* __restrict__ flux = reinterpret_cast<float*>(a.flux);
+  const uint64_t n = min((uint64_t)*a.sur_count, (uint64_t)a.sur_cap);
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + wv) * kWave; base < n; base += waves * kWave) {
+    const uint64_t j = base + lane;
+    const bool ok = j < n;
+    SurEntry e{0.5f, 0, 0};
+    if (ok) e = a.sur_list[j];
+    const BandConst bcv = a.bc[e.band];
+    const float z = e.z, k = ok ? bcv.kf : 0.1f;
+    float y1;
+    mlp_eval_wave<SPLIT, 1, 1>(m, &m->frag[0][0][0], z, k, lane, &y1);
+    if (ok) {
+      const float k2 = k * k;
+      const float loss = bcv.wf[0] * k2 + bcv.wf[1] * mlp_alpha1(z, k, y1) +
+                         bcv.wf[2] * (0.5f * k2 * (k2 + 2.0f * z * z));
+      const int nss = (int)(e.idx_nss >> kSurNssShift);
+      atomicAdd(flux + (e.idx_nss & ((1ull << kSurNssShift) - 1ull)), -loss / (float)nss);
+    }
+    const uint64_t okm = __ballot(ok);
+    if (lane == 0) atomicAdd(m->ctr, (unsigned long long)__popcll(okm));
+  }
 }
 
 // Bilinear interpolation of the three functions (Sect. 2.2.3); k outside the
@@ -682,7 +729,7 @@ __device__ __forceinline__ float interp_rows(const float* zb, int lane, const ch
 template <int PREC, int MODEL, class T>
 __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
                                           int bnd, const BatchArgs& a, const T* __restrict__ tb,
-                                          __bf16* act) {
+                                          uint64_t idx_nss, bool act_lane) {
   static_assert(MODEL != kModelMAKhat || sizeof(T) == 4, "khat runs in the float path");
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   T acc = T(0);
@@ -740,9 +787,7 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
              bc->wf[2] * zb[(2 * kZChunk + s) * kWave + lane];
   } else if (MODEL == kModelMA) {
     if constexpr (SUR) {
-      const MlpDev* __restrict__ mlp = reinterpret_cast<const MlpDev*>(a.mlp);
-      for (int s = 0; s < ns; ++s)
-        acc += ma_loss_surrogate<PREC == kPrecSurrogate ? 1 : 0>(zb[s * kWave + lane], bc, mlp, act, lane);
+      acc = sur_loss_sum(zb, ns, lane, bc, bnd, a, idx_nss, act_lane);
     } else {
       for (int s = 0; s < ns; ++s) acc += ma_loss<T>(zb[s * kWave + lane], bc);
     }
@@ -768,9 +813,6 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
   const int wv = threadIdx.x / kWave;
   constexpr int planes = MODEL == kModelMAKhat ? 3 : 1;
   T* zb = reinterpret_cast<T*>(lds_raw) + wv * (planes * kZChunk * kWave);
-  __bf16* act = SUR ? reinterpret_cast<__bf16*>(lds_raw + (kBlock / kWave) * kZChunk * kWave * sizeof(T)) +
-                          wv * (kMlpLdsPerWave / 2)
-                    : nullptr;
   const T far_out = T(1e30);
   const T* __restrict__ gtab = reinterpret_cast<const T*>(a.gtab);
   T* __restrict__ flux = reinterpret_cast<T*>(a.flux);
@@ -893,6 +935,11 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         }
       }
     };
+    // flux element and subsample count of a point left to the network
+    auto sur_idx = [&](int bnd, int i) -> uint64_t {
+      if constexpr (!SUR) return 0;
+      return (uint64_t)(fo + (int64_t)(bnd - b0) * cnt + i) | ((uint64_t)nss << kSurNssShift);
+    };
     auto finish = [&](T acc, const BandConst& bcv, int bnd, int i, bool act_lane) {
       if constexpr (MODEL == kModelMAKhat) acc *= T(bcv.kf * bcv.kf * inv_khat2);
       // a band whose radius ratio is not positive and finite, or an orbit
@@ -926,7 +973,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         for (int bnd = b0; bnd < b1; ++bnd) {
           // band constants once per band, by scalar loads
           const BandConst bcv = load_uniform(a.bc + bnd);
-          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride, act),
+          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
+                                            sur_idx(bnd, i), act_lane),
                  bcv, bnd, i, act_lane);
         }
       } else {
@@ -937,7 +985,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
           for (int s0 = 0; s0 < nss; s0 += kZChunk) {
             const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
             orbit_chunk(tm, dmid, s0, ns, false);
-            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride, act);
+            acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
+                                              sur_idx(bnd, i), act_lane);
           }
           finish(acc, bcv, bnd, i, act_lane);
         }
@@ -964,23 +1013,10 @@ __global__ void k_loglike_reduce(const double* __restrict__ partial, const int32
 }
 
 size_t batch_lds_bytes(int prec, int model) {
-  size_t z = (size_t)(kBlock / kWave) * kZChunk * kWave * (prec == kPrecFP64 ? 8 : 4) * (model == kModelMAKhat ? 3 : 1);
-  if (prec == kPrecSurrogate || prec == kPrecSurrogateBf16) z += (size_t)(kBlock / kWave) * kMlpLdsPerWave;
-  return z;
+  return (size_t)(kBlock / kWave) * kZChunk * kWave * (prec == kPrecFP64 ? 8 : 4) * (model == kModelMAKhat ? 3 : 1);
 }
 
-hipError_t prepare_batch_kernels() {
-  const int lds = (int)batch_lds_bytes(kPrecSurrogate, kModelMA);
-  const void* fns[4] = {(const void*)k_lc_batch<kPrecSurrogate, kModelMA, false>,
-                        (const void*)k_lc_batch<kPrecSurrogateBf16, kModelMA, false>,
-                        (const void*)k_lc_batch<kPrecSurrogate, kModelMA, true>,
-                        (const void*)k_lc_batch<kPrecSurrogateBf16, kModelMA, true>};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
+hipError_t prepare_batch_kernels() { return hipSuccess; }
 
 // The flux-writing batch kernel for (prec, model), for occupancy queries.
 static const void* batch_kernel(int prec, int model) {
@@ -1054,6 +1090,16 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
     const size_t lds = batch_lds_bytes(prec, model);
     if (a.obs) launch_main<true>(a, prec, model, dim3(workgroups), lds, s);
     else launch_main<false>(a, prec, model, dim3(workgroups), lds, s);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if ((prec == kPrecSurrogate || prec == kPrecSurrogateBf16) && a.sur_cap > 0) {
+    // the network over the points the first pass left to it (sur_grid
+    // workgroups, a few per compute unit)
+    if (prec == kPrecSurrogate)
+      hipLaunchKernelGGL(k_sur_net<1>, dim3(a.sur_grid), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_sur_net<0>, dim3(a.sur_grid), dim3(kBlock), 0, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
   }

@@ -109,12 +109,12 @@ static hipError_t gemm(int M, int N, int64_t K, const float* A, int64_t sa_i, in
   return hipGetLastError();
 }
 
-// features x = (2 z/(1+k) - 1, (k - k0)/ks)
+// features x = (2 sqrt(1 - z/(1-k)) - 1, (k - k0)/ks)
 __global__ void k_features(const float* __restrict__ zk, int64_t n, float* __restrict__ x) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const float z = zk[2 * i], k = zk[2 * i + 1];
-    x[2 * i] = 2.0f * z / (1.0f + k) - 1.0f;
+    x[2 * i] = mlp_feature_s(z, k);
     x[2 * i + 1] = (k - kFeatK0) * kFeatKS;
   }
 }
@@ -172,9 +172,12 @@ __global__ void k_colsum(int64_t n, int width, const float* __restrict__ g, floa
   if (threadIdx.x == 0) out[j] = red[0];
 }
 
-// Weighted squared error in the network's units y = alpha / k^2, with weight
-// ((k/0.3)^4 + 1e-3): the flux error is about k^2 |dy|, so large k needs the
-// small relative error.  dout = dLoss/dy of the mean; per-block partial sums.
+// Weighted squared error of the three outputs against their targets
+//   t0 = lambda_e/k^2, t1 = (alpha_1/k^2 - sqrt(1 - z^2))/k^2, t2 = eta_d/k^2
+// with per-row weight w(k) = (k/0.3)^8 + 1e-5 times (0.1, 1, 0.1): the alpha_1
+// error is k^4 |dy1|, so w follows its square; the polynomial outputs (the
+// batch path does not read them) get a tenth.  dout = dLoss/dy of the mean
+// over rows and outputs; per-block partial sums of the loss.
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ zk,
                                              const double* __restrict__ alpha, int64_t n,
                                              float* __restrict__ dout, float* __restrict__ part) {
@@ -182,15 +185,17 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
   float s = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float k = zk[2 * i + 1];
-    const double k2 = (double)k * k;
-    const float kk = k / 0.3f;
-    const float w = kk * kk * kk * kk + 1e-3f;
+    const double z = zk[2 * i], k = zk[2 * i + 1];
+    const double k2 = k * k;
+    const double kk = k / 0.3, kk2 = kk * kk, kk4 = kk2 * kk2;
+    const double w = kk4 * kk4 + 1e-5;
+    const double t[3] = {alpha[3 * i] / k2, (alpha[3 * i + 1] / k2 - sqrt(fmax(0.0, 1.0 - z * z))) / k2,
+                         alpha[3 * i + 2] / k2};
     for (int c = 0; c < 3; ++c) {
-      const float t = (float)(alpha[3 * i + c] / k2);
-      const float d = y[3 * i + c] - t;
-      s += w * d * d / (float)(3 * n);
-      dout[3 * i + c] = 2.0f * w * d / (float)(3 * n);
+      const float wc = (float)(c == 1 ? w : 0.1 * w);
+      const float d = y[3 * i + c] - (float)t[c];
+      s += wc * d * d / (float)(3 * n);
+      dout[3 * i + c] = 2.0f * wc * d / (float)(3 * n);
     }
   }
   red[threadIdx.x] = s;
@@ -218,56 +223,57 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict
 // ---------------------------------------------------------------------------
 // Inference
 // ---------------------------------------------------------------------------
+// Device copy of the network: W1, biases and W4 as they are; W2 and W3 as
+// MFMA A-operand fragments in hi/lo bf16, columns in mlp_pi order
+// (fragment (t, s) of lane l: W[16t + l % 16][mlp_pi(s, l / 16, j)], j = 0..7).
 __global__ void k_mlp_pack(const pt_mlp w, MlpDev* __restrict__ m) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kH * kH; i += stride) {
-    const float a = w.W2[i], b = w.W3[i];
-    const __bf16 ah = (__bf16)a, bh = (__bf16)b;
-    m->W2hi[i] = ah; m->W2lo[i] = (__bf16)(a - (float)ah);
-    m->W3hi[i] = bh; m->W3lo[i] = (__bf16)(b - (float)bh);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * kFragPerLayer; e += stride) {
+    const int layer = (int)(e / kFragPerLayer), f = (int)(e % kFragPerLayer);
+    const int t = f / 256, s = (f / 64) % 4, lane = f % 64;
+    const float* W = layer == 0 ? w.W2 : w.W3;
+    bf16x8 hi, lo;
+    for (int j = 0; j < 8; ++j) {
+      const float v = W[(16 * t + (lane & 15)) * kH + mlp_pi(s, lane >> 4, j)];
+      const __bf16 h = (__bf16)v;
+      hi[j] = h;
+      lo[j] = (__bf16)(v - (float)h);
+    }
+    m->frag[layer][0][f] = hi;
+    m->frag[layer][1][f] = lo;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * kH; i += stride) {
     if (i < 2 * kH) m->W1[i] = w.W1[i];
     if (i < kH) { m->b1[i] = w.b1[i]; m->b2[i] = w.b2[i]; m->b3[i] = w.b3[i]; }
-    if (i < 3 * kH) m->W4[i] = w.W4[i];
+    m->W4[i] = w.W4[i];
     if (i < 3) m->b4[i] = w.b4[i];
   }
 }
 
-// Trust map: one wave per cell, 64 points on an 8 x 8 grid inside it (cell
-// edges included); the cell is trusted when the bound on the flux error,
-// 2|d lambda_e| + 4|d lambda_d| + 2|d eta_d| (the largest limb-darkening
-// weights of the quadratic law with coefficients from uniform (q1, q2)), is
-// below tol at every grid point.
+// Error map: one wave per cell, 64 points on an 8 x 8 grid inside it (cell
+// edges included, s = z/(1-k) and k; points in the fallback band are served
+// exactly and skipped); the cell's entry is the largest |alpha_1 error| of the
+// network against the exact double model, in the same float arithmetic the
+// batch path uses (z and k in float, the network on its MFMA path).  A cell
+// with a non-finite error gets +inf (never used).
 template <int SPLIT>
-__global__ __launch_bounds__(256) void k_mlp_trust(const MlpDev* __restrict__ m, float tol,
-                                                   uint8_t* __restrict__ cells) {
-  extern __shared__ unsigned char lds_raw[];
+__global__ __launch_bounds__(256) void k_mlp_errmap(MlpDev* __restrict__ m) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __bf16* act = reinterpret_cast<__bf16*>(lds_raw) + wv * (kMlpLdsPerWave / 2);
   const int cell = blockIdx.x * 4 + wv;
   if (cell >= kTrustNC * kTrustNK) return;          // wave-uniform
   const int ci = cell % kTrustNC, cj = cell / kTrustNC;
   const float dk = (m->k_hi - m->k_lo) / kTrustNK;
-  const float c = (ci + (lane % 8) / 7.0f) / kTrustNC;
   const float k = m->k_lo + dk * (cj + (lane / 8) / 7.0f);
-  const float z = fminf(c, 0.9999999f) * (1.0f + k);
-  float y[3];
-  mlp_eval_wave<SPLIT>(m, z, k, act, lane, y);
+  const float sc = (ci + (lane % 8) / 7.0f) / kTrustNC;
+  const float z = fminf(sc, 0.9999999f) * (1.0f - k);
+  float y1;
+  mlp_eval_wave<SPLIT, 1, 1>(m, &m->frag[0][0][0], z, k, lane, &y1);
   const MaAlpha<double> ex = ma_alpha_exact<double>((double)z, (double)k);
-  const double k2 = (double)k * k;
-  const bool band = fabsf(z - (1.0f - k)) < m->band || fabsf(z - (1.0f + k)) < m->band;
-  float e = (float)(2.0 * fabs(k2 * y[0] - ex.le) + 4.0 * fabs(k2 * y[1] - ex.ld) + 2.0 * fabs(k2 * y[2] - ex.ed));
-  if (band) e = 0.0f;                               // served exactly anyway
-  if (!(e <= tol)) e = 1e30f;
+  const bool served = z < (1.0f - k) - m->band;
+  float e = served ? (float)fabs((double)mlp_alpha1(z, k, y1) - ex.ld) : 0.0f;
+  if (!(e <= 1e30f)) e = INFINITY;
   for (int off = 32; off > 0; off >>= 1) e = fmaxf(e, __shfl_xor(e, off));
-  if (lane == 0) cells[cell] = e <= tol ? 1 : 0;
-}
-
-__global__ void k_pack_trust(const uint8_t* __restrict__ cells, MlpDev* __restrict__ m) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= kTrustNC * kTrustNK / 32) return;
-  uint32_t bits = 0;
-  for (int b = 0; b < 32; ++b) bits |= (uint32_t)(cells[w * 32 + b] & 1) << b;
-  m->trust[w] = bits;
+  if (lane == 0) m->err[cell] = e;
 }
 
 __global__ void k_set_params(MlpDev* m, float band, float k_lo, float k_hi, int split, unsigned long long* ctr) {
@@ -275,13 +281,16 @@ __global__ void k_set_params(MlpDev* m, float band, float k_lo, float k_hi, int 
   ctr[0] = 0ull; ctr[1] = 0ull;
 }
 
-// Surrogate values at (z, k) rows, with the exact fallback: out = alpha.
+// Surrogate values at (z, k) rows, with the exact fallback: out = (lambda_e,
+// alpha_1, eta_d).  A row takes the network (alpha_1 from it, lambda_e and
+// eta_d from their polynomials) where its cell's error, times 4 (the largest
+// weight of alpha_1 in the flux loss of a quadratic law with uniform (q1, q2)
+// coefficients), is within kSurrogateFluxTol; elsewhere the exact double
+// functions.
 template <int SPLIT>
 __global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev* __restrict__ m, const double* __restrict__ zk,
                                                   int64_t n, double* __restrict__ out) {
-  extern __shared__ unsigned char lds_raw[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __bf16* act = reinterpret_cast<__bf16*>(lds_raw) + wv * (kMlpLdsPerWave / 2);
   const int64_t waves = (int64_t)gridDim.x * 4;
   for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 64; base < n; base += waves * 64) {
     const int64_t i = base + lane;
@@ -289,13 +298,16 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev* __restrict__ m, 
     const double zd = act_lane ? zk[2 * i] : 0.5, kd = act_lane ? zk[2 * i + 1] : 0.1;
     const float z = (float)zd, k = (float)kd;
     const bool in = z >= 0.0f && z < 1.0f + k;
-    const bool tr = in && mlp_trusted(m, z, k);
-    float y[3] = {0, 0, 0};
-    if (__any(tr)) mlp_eval_wave<SPLIT>(m, z, k, act, lane, y);   // wave-uniform
+    const int cell = in ? mlp_cell(m, z, k) : -1;
+    const bool tr = cell >= 0 && 4.0f * m->err[cell] <= kSurrogateFluxTol;
+    float y1 = 0.0f;
+    if (__any(tr)) mlp_eval_wave<SPLIT, 1, 1>(m, &m->frag[0][0][0], z, k, lane, &y1);   // wave-uniform
     double a0 = 0, a1 = 0, a2 = 0;
     if (tr) {
       const double k2 = (double)k * k;
-      a0 = k2 * y[0]; a1 = k2 * y[1]; a2 = k2 * y[2];
+      a0 = k2;
+      a1 = mlp_alpha1(z, k, y1);
+      a2 = 0.5 * k2 * (k2 + 2.0 * (double)z * z);
     } else if (in) {
       const MaAlpha<double> ex = ma_alpha_exact<double>(zd, kd);
       a0 = ex.le; a1 = ex.ld; a2 = ex.ed;
@@ -310,16 +322,14 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev* __restrict__ m, 
 template <int SPLIT>
 __global__ __launch_bounds__(256) void k_mlp_infer(const MlpDev* __restrict__ m, const float* __restrict__ zk,
                                                    int64_t n, float* __restrict__ out) {
-  extern __shared__ unsigned char lds_raw[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __bf16* act = reinterpret_cast<__bf16*>(lds_raw) + wv * (kMlpLdsPerWave / 2);
   const int64_t waves = (int64_t)gridDim.x * 4;
   for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 64; base < n; base += waves * 64) {
     const int64_t i = base + lane;
     const bool ok = i < n;
     const float z = ok ? zk[2 * i] : 0.5f, k = ok ? zk[2 * i + 1] : 0.1f;
     float y[3];
-    mlp_eval_wave<SPLIT>(m, z, k, act, lane, y);
+    mlp_eval_wave<SPLIT, 0, 3>(m, &m->frag[0][0][0], z, k, lane, y);
     if (ok) { out[3 * i] = y[0]; out[3 * i + 1] = y[1]; out[3 * i + 2] = y[2]; }
   }
 }
@@ -520,26 +530,17 @@ pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, d
   st.k_hi = (float)k_hi;
   const char* sp = getenv("PT_MLP_SPLIT");
   st.split = (sp && sp[0] == '0') ? 0 : 1;
-  hipLaunchKernelGGL(k_mlp_pack, dim3(grid1(kH * kH)), dim3(256), 0, s, *w, st.dev_ptr);
+  hipLaunchKernelGGL(k_mlp_pack, dim3(grid1(2 * kFragPerLayer)), dim3(256), 0, s, *w, st.dev_ptr);
   hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, s, st.dev_ptr, st.band, st.k_lo, st.k_hi, st.split, st.ctr);
-  uint8_t* cells = nullptr;
-  MLP_HIP(hipMallocAsync((void**)&cells, kTrustNC * kTrustNK, s));
-  const size_t lds = 4 * kMlpLdsPerWave;
-  const float tol = 8e-6f;
-  if (st.split) {
-    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_trust<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_mlp_trust<1>, dim3(kTrustNC * kTrustNK / 4), dim3(256), lds, s, st.dev_ptr, tol, cells);
-  } else {
-    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_trust<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_mlp_trust<0>, dim3(kTrustNC * kTrustNK / 4), dim3(256), lds, s, st.dev_ptr, tol, cells);
-  }
-  hipLaunchKernelGGL(k_pack_trust, dim3(grid1(kTrustNC * kTrustNK / 32)), dim3(256), 0, s, cells, st.dev_ptr);
-  std::vector<uint8_t> host(kTrustNC * kTrustNK);
-  MLP_HIP(hipMemcpyAsync(host.data(), cells, host.size(), hipMemcpyDeviceToHost, s));
+  if (st.split)
+    hipLaunchKernelGGL(k_mlp_errmap<1>, dim3(kTrustNC * kTrustNK / 4), dim3(256), 0, s, st.dev_ptr);
+  else
+    hipLaunchKernelGGL(k_mlp_errmap<0>, dim3(kTrustNC * kTrustNK / 4), dim3(256), 0, s, st.dev_ptr);
+  std::vector<float> host(kTrustNC * kTrustNK);
+  MLP_HIP(hipMemcpyAsync(host.data(), st.dev_ptr->err, host.size() * sizeof(float), hipMemcpyDeviceToHost, s));
   MLP_HIP(hipStreamSynchronize(s));
-  hipFree(cells);
   size_t ntr = 0;
-  for (uint8_t c : host) ntr += c;
+  for (float e : host) ntr += 4.0f * e <= kSurrogateFluxTol;
   st.trusted_fraction = (double)ntr / host.size();
   st.ready = true;
   MLP_HIP(hipGetLastError());
@@ -555,15 +556,11 @@ pt_status pt_surrogate_eval(const double* zk, int64_t n, double* out, void* stre
   if (!m) return set_error(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
   if (n == 0) return PT_OK;
   hipStream_t s = (hipStream_t)stream;
-  const size_t lds = 4 * kMlpLdsPerWave;
   const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
-  if (surrogate_split(dev)) {
-    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_eval<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_mlp_eval<1>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
-  } else {
-    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_eval<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_mlp_eval<0>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
-  }
+  if (surrogate_split(dev))
+    hipLaunchKernelGGL(k_mlp_eval<1>, dim3(blocks), dim3(256), 0, s, m, zk, n, out);
+  else
+    hipLaunchKernelGGL(k_mlp_eval<0>, dim3(blocks), dim3(256), 0, s, m, zk, n, out);
   MLP_HIP(hipGetLastError());
   return PT_OK;
 }
@@ -577,15 +574,11 @@ pt_status pt_mlp_infer(const float* zk, int64_t n, float* out, void* stream) {
   if (!m) return set_error(PT_ERR_UNSUPPORTED, "no surrogate weights installed (pt_surrogate_set)");
   if (n == 0) return PT_OK;
   hipStream_t s = (hipStream_t)stream;
-  const size_t lds = 4 * kMlpLdsPerWave;
   const int blocks = (int)std::min<int64_t>(8192, (n + 255) / 256);
-  if (surrogate_split(dev)) {
-    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_infer<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_mlp_infer<1>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
-  } else {
-    MLP_HIP(hipFuncSetAttribute((const void*)k_mlp_infer<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_mlp_infer<0>, dim3(blocks), dim3(256), lds, s, m, zk, n, out);
-  }
+  if (surrogate_split(dev))
+    hipLaunchKernelGGL(k_mlp_infer<1>, dim3(blocks), dim3(256), 0, s, m, zk, n, out);
+  else
+    hipLaunchKernelGGL(k_mlp_infer<0>, dim3(blocks), dim3(256), 0, s, m, zk, n, out);
   MLP_HIP(hipGetLastError());
   return PT_OK;
 }

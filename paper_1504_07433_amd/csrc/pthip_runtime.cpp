@@ -197,7 +197,8 @@ struct Plan {
   std::vector<int64_t> t_count;
   std::vector<int32_t> nss, band_off;
   DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, gtab64, queue, khat, ztab,
-      ltab;
+      ltab, sur;
+  int64_t sur_cap = 0;   // surrogate: list entries (sur holds a 256-byte counter line, then the list)
   std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
   LaunchShape shape;
   bool tuned = false;
@@ -442,6 +443,14 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   PT_HIP(p->queue.ensure(kQueues * kQueueStride * sizeof(unsigned int)));
   PT_HIP(hipMemset(p->queue.p, 0, kQueues * kQueueStride * sizeof(unsigned int)));
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
+  if (prec == PT_PREC_SURROGATE) {
+    // every (subsample, exposure, band) point may be left to the network, up
+    // to kSurListMax per call (the rest take the float path)
+    int64_t pts = 0;
+    for (size_t i = 0; i < n; ++i) pts += (int64_t)(b->band_off[i + 1] - b->band_off[i]) * b->t_count[i] * b->nss[i];
+    p->sur_cap = std::max<int64_t>(64, std::min<int64_t>(pts, kSurListMax));
+    PT_HIP(p->sur.ensure(256 + (size_t)p->sur_cap * sizeof(SurEntry)));
+  }
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
     const size_t nb = std::max<size_t>(1, (size_t)p->n_band);
     const size_t es = prec == PT_PREC_FP64 ? 8 : 4;
@@ -496,7 +505,15 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
   a->nldc = p->nldc;
   a->npol = p->npol;
   a->model = p->model;
-  if (p->prec == PT_PREC_SURROGATE) a->mlp = surrogate_device_ptr(p->dev);
+  if (p->prec == PT_PREC_SURROGATE) {
+    a->mlp = surrogate_device_ptr(p->dev);
+    if (!obs) {   // the likelihood path evaluates every point in its own pass
+      a->sur_count = (unsigned int*)p->sur.p;
+      a->sur_list = (SurEntry*)((char*)p->sur.p + 256);
+      a->sur_cap = p->sur_cap;
+      a->sur_grid = 2 * std::max(1, cu_count());
+    }
+  }
   if (p->model == PT_MODEL_MA_KHAT) a->khat = (double*)p->khat.p;
   if (p->model == PT_MODEL_MA_INTERP) {
     if (p->dev < 0 || p->dev >= 16 || !g_matab[p->dev].ready)

@@ -36,16 +36,15 @@ class Surrogate:
 
     # -- data -------------------------------------------------------------------------
     def make_data(self, n: int, seed: int = 5):
-        """(z, k) pairs of the training recipe and their exact targets; rows at
-        z >= 1 + k (flux 1) and inside the fallback band are kept: the network
-        learns zeros there and is never asked."""
+        """(z, k) pairs of the training recipe (inside the stellar disc, outside
+        the fallback band of the inner contact) and the exact functions there."""
         zk = W.config5_training(seed=seed, n=n)
         zk64 = torch.as_tensor(zk, device=self.device)
         alpha = pthip.mlp_datagen(zk64)
         return zk64.float().contiguous(), alpha
 
     # -- training ---------------------------------------------------------------------
-    def train(self, zk32, alpha, steps: int, batch: int = 65536, lr: float = 2e-3, lr_min: float = 2e-5,
+    def train(self, zk32, alpha, steps: int, batch: int = 65536, lr: float = 2e-3, lr_min: float = 1e-6,
               log_every: int = 500, seed: int = 0):
         g = torch.Generator(device=self.device)
         g.manual_seed(seed)

@@ -1,11 +1,13 @@
 """Trains the Mandel-Agol surrogate on the GPU and writes a checkpoint.
 
-    python -m paper_1504_07433_amd.train_surrogate --steps 20000 --out surrogate.npz
+    python -m paper_1504_07433_amd.train_surrogate --steps 60000 --out surrogate.npz
 
-Training data: 1e7 (z, k) pairs with k ~ U(0.01, 0.3), z ~ U(0, 1.4) plus 20 %
-near z in {k, 1-k, 1+k}; targets are the exact functions from the library's
-double-precision kernel.  Forward, loss, backward and Adam all run in
-libpthip.so.  Prints one progress line per log interval.
+Training data: 1e7 (z, k) pairs inside the stellar disc, k ~ U(0.01, 0.3),
+z/(1-k-1e-3) ~ U(0, 1), plus 20 % denser towards the inner contact; targets
+are the exact functions from the library's double-precision kernel.
+Forward, loss, backward and Adam all run in libpthip.so; one cosine learning
+rate schedule from --lr to 1e-6 over the run.  Prints one progress line per
+2000 steps.
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ DEFAULT_CKPT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=10_000_000)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=60000)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=5)
@@ -47,7 +49,7 @@ def main():
         # one cosine schedule over the whole run, continued across chunks
         lr_hi = args.lr * 0.5 * (1 + torch.cos(torch.tensor(3.14159265 * done / args.steps)).item())
         lr_lo = args.lr * 0.5 * (1 + torch.cos(torch.tensor(3.14159265 * (done + n) / args.steps)).item())
-        hist = s.train(zk32, alpha, steps=n, batch=args.batch, lr=max(lr_hi, 2e-5), lr_min=max(lr_lo, 2e-5),
+        hist = s.train(zk32, alpha, steps=n, batch=args.batch, lr=max(lr_hi, 1e-6), lr_min=max(lr_lo, 1e-6),
                        log_every=n, seed=args.seed + done)
         done += n
         print(json.dumps({"phase": "train", "step": s.step, "loss": hist[-1][1],

@@ -179,24 +179,23 @@ def config4(seed: int = 4, n_lc: int = 4096, n_min: int = 500,
 
 
 def config5_training(seed: int = 5, n: int = 10_000_000,
-                     k_range=(0.01, 0.3), z_max: float = 1.4,
-                     contact_frac: float = 0.2, contact_width: float = 0.05):
-    """(z, k) training pairs for the surrogate: k~U(.01,.3), z~U(0,1.4), plus
-    an extra ``contact_frac`` of samples within +-0.05 of z in {k, 1-k, 1+k}.
+                     k_range=(0.01, 0.3), band: float = 1e-3,
+                     contact_frac: float = 0.2, contact_width: float = 0.1):
+    """(z, k) training pairs for the surrogate, which serves the inside of the
+    stellar disc: k ~ U(.01, .3), s = z/(1 - k - band) ~ U(0, 1), plus an extra
+    ``contact_frac`` of samples with s = 1 - ``contact_width`` U^2 (denser
+    towards the inner contact z = 1 - k).  z is rounded to float (the network's
+    input type) so that targets are exact at the inputs the network sees.
     Returns an [m, 2] float64 array of (z, k)."""
     rng = np.random.default_rng(seed)
-    k = rng.uniform(*k_range, n)
-    z = rng.uniform(0.0, z_max, n)
     m = int(round(contact_frac * n))
-    kc = rng.uniform(*k_range, m)
-    which = rng.integers(0, 3, m)
-    centre = np.where(which == 0, kc, np.where(which == 1, 1.0 - kc, 1.0 + kc))
-    zc = np.clip(centre + rng.uniform(-contact_width, contact_width, m), 0.0, z_max)
-    zk = np.empty((n + m, 2))
-    zk[:n, 0] = z; zk[:n, 1] = k
-    zk[n:, 0] = zc; zk[n:, 1] = kc
-    perm = rng.permutation(n + m)
-    return zk[perm]
+    k = rng.uniform(*k_range, n + m)
+    s = rng.uniform(0.0, 1.0, n + m)
+    s[n:] = 1.0 - contact_width * rng.uniform(0.0, 1.0, m) ** 2
+    z = (s * (1.0 - k - band)).astype(np.float32).astype(np.float64)
+    k = k.astype(np.float32).astype(np.float64)
+    zk = np.stack([np.minimum(z, np.nextafter(1.0 - k - band, 0.0)), k], 1)
+    return zk[rng.permutation(n + m)]
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
