@@ -73,9 +73,10 @@ PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second
 HBM_PEAK = 8.0e12
 # MFMA work of one network evaluation per point: two 128 x 128 layers on
 # v_mfma_f32_16x16x32_bf16 (the 2 -> 128 and 128 -> 3 layers run on the VALU),
-# 2 x 128 x 128 x 2 flops, three products each with the hi/lo split.
+# 2 x 128 x 128 x 2 flops; three bf16 products each with the hi/lo split (one
+# with PT_MLP_SPLIT=0).
 F_NET_MFMA = 2 * 128 * 128 * 2
-NET_PRODUCTS = 3
+NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 # Hardware counters of k_lc_batch<fp32, MA> per workload (profiles/
 # k_lc_batch_fp32_ma_<workload>_counters.txt): wave64 VALU instructions per
 # launch, FETCH_SIZE and WRITE_SIZE in KiB per launch.  HBM bytes = FETCH_SIZE
@@ -96,7 +97,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-side", action="store_true", help="skip the side legs")
     ap.add_argument("--autotune", action="store_true",
-                    help="tune the launch shape of every leg first and rewrite the tuned-shape cache")
+                    help="tune the launch shape of every leg first and write the tuned-shape cache")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tuned-shape cache read at start (and written by --autotune)")
     ap.add_argument("--mode", choices=("full", "kernel", "units"), default="full",
                     help="kernel: only the timed launches of one leg (for profilers); units: "
                          "divergence-free launches of each unit of work, for counting operations per unit")
@@ -346,7 +349,7 @@ def main():
     if args.mode == "units":
         unit_probes()
         return
-    tuned = pthip.tune_load(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else 0
+    tuned = pthip.tune_load(args.tune_cache) if os.path.exists(args.tune_cache) and not args.autotune else 0
     sur = None
     if os.path.exists(SURROGATE_CKPT):
         from paper_1504_07433_amd.surrogate import Surrogate
@@ -527,7 +530,7 @@ def main():
         del d4, f4, f464
         line["paths"] = paths
     if args.autotune:
-        pthip.tune_save(TUNE_CACHE)
+        pthip.tune_save(args.tune_cache)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(b3)
     print(json.dumps(line), flush=True)

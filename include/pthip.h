@@ -301,14 +301,20 @@ pt_status pt_mlp_adam_step(pt_mlp* w, const pt_mlp* grad, pt_mlp* m, pt_mlp* v, 
                            float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Installs trained weights for PT_PREC_SURROGATE (the library keeps its own
- * BF16 copies; the caller's buffers may be freed afterwards).  Points within
- * fallback_band of z = 1 - k or z = 1 + k, and k outside [k_lo, k_hi], use
- * the exact functions. */
+ * BF16 copies; the caller's buffers may be freed afterwards) and builds the
+ * network's error map against the exact model.  The network serves the
+ * inside of the stellar disc, 0 <= z < 1 - k - fallback_band, for k in
+ * [k_lo, k_hi]; every other point uses the exact functions.  Inference runs
+ * bf16 MFMA products with float accumulation, weights and activations split
+ * into bf16 hi + lo parts (three products); with the environment variable
+ * PT_MLP_SPLIT=0 at this call, one product of the hi parts.  Synchronises the
+ * stream. */
 pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, double k_hi,
                            void* stream);
 
-/* Fraction of trust-map cells (over c = z/(1+k) in [0,1), k in [k_lo, k_hi])
- * in which the exact model accepted the installed network (-1 on error). */
+/* Fraction of error-map cells (over s = z/(1-k) in [0,1), k in [k_lo, k_hi])
+ * whose network error keeps the flux of every quadratic law with uniform
+ * (q1, q2) coefficients within tolerance (-1 on error). */
 double pt_surrogate_trusted_fraction(void);
 
 /* Point counters of the installed surrogate on this device: out[0] = points
@@ -326,8 +332,11 @@ pt_status pt_surrogate_counters(uint64_t* out, int32_t reset);
  * no fallback (for checking inference against pt_mlp_forward). */
 pt_status pt_mlp_infer(const float* zk, int64_t n, float* out, void* stream);
 
-/* Evaluates the installed surrogate's three functions at zk[n][2] (double),
- * out[n][3] (double), with the same fallback rules as the batch path. */
+/* Evaluates the installed surrogate's three functions (lambda_e, lambda_d +
+ * 2/3 Theta(k - z), eta_d) at zk[n][2] (double), out[n][3] (double): the
+ * network's where its error map accepts it for any quadratic law with uniform
+ * (q1, q2) coefficients (lambda_e and eta_d then from their polynomials),
+ * the exact double functions elsewhere. */
 pt_status pt_surrogate_eval(const double* zk, int64_t n, double* out, void* stream);
 
 #ifdef __cplusplus

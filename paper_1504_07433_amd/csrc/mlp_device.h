@@ -111,9 +111,8 @@ __device__ __forceinline__ void mlp_split8(const float h[8], bf16x8* hi, bf16x8*
 // Output tiles in turn, the next tile's four fragments loaded while the
 // current tile's products run; the scheduling barrier keeps the compiler
 // from hoisting further loads (their registers would not fit).
-template <int SPLIT>
-__device__ __forceinline__ void mlp_layer(const bf16x8* __restrict__ w_hi, const bf16x8* __restrict__ w_lo,
-                                          const bf16x8 oh[4][4], const bf16x8 ol[4][4], int lane,
+template <int SPLIT, class F>
+__device__ __forceinline__ void mlp_layer(F w_hi, F w_lo, const bf16x8 oh[4][4], const bf16x8 ol[4][4], int lane,
                                           f32x4 acc[8][4]) {
   bf16x8 ch[4], cl[4], nh[4], nl[4];
 #pragma unroll
@@ -186,15 +185,24 @@ __device__ __forceinline__ const T* mlp_opaque(const T* p) {
   return (const T*)v;
 }
 
+// The same for a fragment pointer into LDS, kept in the LDS address space so
+// that its loads stay ds_read instructions.
+__device__ __forceinline__ const __attribute__((address_space(3))) bf16x8* mlp_opaque_lds(
+    const __attribute__((address_space(3))) bf16x8* p) {
+  uint32_t v = (uint32_t)(uintptr_t)p;
+  asm volatile("" : "+v"(v));
+  return (const __attribute__((address_space(3))) bf16x8*)(uintptr_t)v;
+}
+
 // Network for the wave's 64 points (one per lane; every lane of the wave must
-// call it).  frag: the [layer][hi, lo] weight fragments (in global memory or
-// LDS).  Writes outputs O0 .. O0+NOUT-1 of the lane's own point to
-// y[0 .. NOUT-1].
-template <int SPLIT, int O0, int NOUT>
-__device__ __forceinline__ void mlp_eval_wave(const MlpDev* __restrict__ m, const bf16x8* __restrict__ frag,
+// call it).  F: a pointer to weight fragments, in global memory or LDS; layer
+// 2's hi fragments at frag, its lo fragments (used with SPLIT) at frag +
+// kFragPerLayer, layer 3's at frag + layer_stride (+ kFragPerLayer).  Writes
+// outputs O0 .. O0+NOUT-1 of the lane's own point to y[0 .. NOUT-1].
+template <int SPLIT, int O0, int NOUT, class F>
+__device__ __forceinline__ void mlp_eval_wave(const MlpDev* __restrict__ m, F frag, int layer_stride,
                                               float z, float k, int lane, float* y) {
   m = mlp_opaque(m);
-  frag = mlp_opaque(frag);
   const int c = lane & 15, q = lane >> 4;
   const float x0s = mlp_feature_s(z, k), x1s = (k - kFeatK0) * kFeatKS;
   // input layer: the lane's 32 neurons (mlp_pi order) of the points of its
@@ -231,7 +239,7 @@ __device__ __forceinline__ void mlp_eval_wave(const MlpDev* __restrict__ m, cons
   mlp_layer<SPLIT>(frag, frag + kFragPerLayer, oh, ol, lane, acc);
   mlp_act(acc, oh, ol);
   mlp_bias(m->b3, q, acc);
-  mlp_layer<SPLIT>(frag + 2 * kFragPerLayer, frag + 3 * kFragPerLayer, oh, ol, lane, acc);
+  mlp_layer<SPLIT>(frag + layer_stride, frag + layer_stride + kFragPerLayer, oh, ol, lane, acc);
   // output layer: partial sums over the lane's 32 neurons of each point tile,
   // then over the four lanes of the column (q = 0..3)
   float part[NOUT][4];
@@ -264,6 +272,13 @@ __device__ __forceinline__ void mlp_eval_wave(const MlpDev* __restrict__ m, cons
     // the lane's own point is point tile q of its column
     y[o] = m->b4[O0 + o] + (q == 0 ? part[o][0] : q == 1 ? part[o][1] : q == 2 ? part[o][2] : part[o][3]);
   }
+}
+
+// mlp_eval_wave on the device copy's fragments in global memory.
+template <int SPLIT, int O0, int NOUT>
+__device__ __forceinline__ void mlp_eval_wave_global(const MlpDev* __restrict__ m, float z, float k, int lane,
+                                                     float* y) {
+  mlp_eval_wave<SPLIT, O0, NOUT>(m, mlp_opaque(&m->frag[0][0][0]), 2 * kFragPerLayer, z, k, lane, y);
 }
 
 }  // namespace pt

@@ -9,20 +9,31 @@
 
 namespace pt {
 
-// Per-passband constants of a batch, formed on the device each call.
+// Per-passband constants of a batch, formed on the device each call.  The
+// first 32 bytes are what the float Mandel-Agol path reads per band
+// (BandMAView, one scalar load); a band is valid when its radius ratio is
+// positive and its weights finite, and an invalid band has NaN weights.
 struct BandConst {
   double kd;            // radius ratio
-  double wd[5];         // loss weights in double (MA: (1-c)/N, c/N, u2/N; Gimenez: C_0..C_N)
-  float wf[5];          // the same in float
   float kf;             // radius ratio, float
+  float wf[3];          // loss weights in float (MA: (1-c)/N, c/N, u2/N)
   float onepk;          // 1 + k (float), out-of-transit test
   float omk;            // 1 - k (float)
+  double wd[5];         // loss weights in double (MA: the three above; Gimenez: C_0..C_N)
   float inv1pk;         // 1 / (1 + k) (float), Gimenez c = z/(1+k)
-  double inv1pkd;       // 1 / (1 + k) (double)
   int32_t exact;        // k > 1/2: Mandel-Agol through the exact double path
+  double inv1pkd;       // 1 / (1 + k) (double)
   int32_t valid;        // k > 0 and finite weights
+  int32_t pad;
 };
 
+// The leading part of BandConst the float Mandel-Agol band loop reads:
+// exact is kd > 1/2, valid is w0 not NaN.
+struct BandMAView {
+  double kd;
+  float kf, w0, w1, w2, onepk, omk;
+};
+static_assert(offsetof(BandConst, omk) + sizeof(float) == sizeof(BandMAView), "BandMAView is a prefix");
 
 // kPrecSurrogateBf16: the surrogate with bf16-only products (no hi/lo split)
 enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2, kPrecSurrogateBf16 = 3 };
@@ -57,6 +68,13 @@ struct SurEntry {
 };
 constexpr int kSurNssShift = 48;
 constexpr int64_t kSurListMax = int64_t(1) << 26;   // entries per call (1 GiB)
+// The list is split into kSurLists sub-lists of sur_cap / kSurLists entries,
+// each with its own counter on its own 128-byte line (a wave appends to the
+// sub-list of its first flux element's 64-element block): with one counter the
+// appends of every wave of the GPU meet on one address and the first pass
+// ran 9.3 ms instead of 0.6 ms on the spectrophotometric batch.
+constexpr int kSurLists = 64;
+constexpr int kSurListStride = 32;   // unsigned ints between counters
 
 // Everything the persistent batch kernel reads.
 struct BatchArgs {
@@ -95,9 +113,9 @@ struct BatchArgs {
   int32_t model;
   // surrogate
   const void* mlp;      // device MlpDev (bf16 weights) or null
-  SurEntry* sur_list;   // points left to the network [sur_cap]
-  unsigned int* sur_count;  // entries written (reset by the prep kernel)
-  int64_t sur_cap;      // 0: no list, every point takes the float path
+  SurEntry* sur_list;   // points left to the network [sur_cap], kSurLists sub-lists
+  unsigned int* sur_count;  // entries appended per sub-list, kSurListStride apart (reset by the prep kernel)
+  int64_t sur_cap;      // multiple of kSurLists * 64; 0: no list, every point takes the float path
   int32_t sur_grid;     // workgroups of the network pass
   // fused likelihood (obs == null: write flux)
   const void* obs;      // observed flux, same layout and type as flux

@@ -399,15 +399,18 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
     c.wd[0] = (1.0 - su) * inv;
     for (int m = 1; m <= nldc; ++m) c.wd[m] = u[m - 1] * inv;
   }
+  for (int m = 0; m < 5; ++m)
+    if (!isfinite(c.wd[m])) c.valid = 0;
   if (!c.valid)
     for (int m = 0; m < 5; ++m) c.wd[m] = (double)NAN;
-  for (int m = 0; m < 5; ++m) c.wf[m] = float(c.wd[m]);
+  for (int m = 0; m < 3; ++m) c.wf[m] = float(c.wd[m]);
+  c.pad = 0;
   return c;
 }
 
 __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
   if (blockIdx.x == 0 && threadIdx.x < kQueues) a.queue[threadIdx.x * kQueueStride] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x == kQueues && a.sur_count) *a.sur_count = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kSurLists && a.sur_count) a.sur_count[threadIdx.x * kSurListStride] = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_band; i += stride)
     a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
@@ -518,6 +521,13 @@ __device__ __forceinline__ float ma_loss<float>(float z, const BandConst* __rest
   return bc->wf[0] * r.le + bc->wf[1] * r.ld + bc->wf[2] * r.ed;
 }
 
+// The same from the leading part of the band's constants.
+__device__ __forceinline__ float ma_loss_view(float z, const BandMAView& v) {
+  if (z < 0.0f || z >= v.onepk) return 0.0f;
+  const MaAlpha<float> r = ma_alpha_fast(z, v.kf, v.kd, v.kd > 0.5, v.omk);
+  return v.w0 * r.le + v.w1 * r.ld + v.w2 * r.ed;
+}
+
 template <>
 __device__ __forceinline__ double ma_loss<double>(double z, const BandConst* __restrict__ bc) {
   if (z < 0.0 || z >= 1.0 + bc->kd) return 0.0;
@@ -543,15 +553,24 @@ __device__ __forceinline__ T gim_loss(T z, const BandConst* __restrict__ bc, int
 
 // Surrogate path, first pass: a point inside the stellar disc whose
 // error-map cell keeps the band's flux error within tolerance is left to the
-// network (appended to the list, its loss added by k_sur_net); every other
-// in-transit point takes the float path here.  The wave reserves list slots
-// with one atomic; a point that finds the list full takes the float path.
-// Returns the loss summed over the subsamples of the chunk, without the
-// network's points.
+// network (appended to a sub-list chosen by the wave's flux elements, its
+// loss added by k_sur_net);
+// every other in-transit point takes the float path here.  The wave reserves
+// sub-list slots with one atomic; a point that finds its sub-list full takes
+// the float path.  Returns the loss summed over the subsamples of the chunk,
+// without the network's points; n_exact counts the wave's exact in-transit
+// points (wave-uniform, flushed once at the end of the kernel).
 __device__ __forceinline__ float sur_loss_sum(const float* zb, int ns, int lane, const BandConst* __restrict__ bc,
-                                              int bnd, const BatchArgs& a, uint64_t idx_nss, bool act_lane) {
+                                              int bnd, const BatchArgs& a, uint64_t idx_nss, bool act_lane,
+                                              unsigned int& n_exact) {
   const MlpDev* __restrict__ m = reinterpret_cast<const MlpDev*>(a.mlp);
   const float w1 = fabsf(bc->wf[1]);
+  // the sub-list: from the wave's first flux element, so that the points of
+  // different bands and exposure runs spread over the sub-lists
+  const uint64_t idx0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(idx_nss >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)idx_nss);
+  const int sl = (int)(((idx0 & ((1ull << kSurNssShift) - 1ull)) >> 6) % kSurLists);
+  const uint64_t cap_l = (uint64_t)a.sur_cap / kSurLists;
   float acc = 0.0f;
   for (int s = 0; s < ns; ++s) {
     const float z = zb[s * kWave + lane];
@@ -561,17 +580,16 @@ __device__ __forceinline__ float sur_loss_sum(const float* zb, int ns, int lane,
     const uint64_t netm = __ballot(net);
     if (netm) {
       unsigned int base = 0;
-      if (lane == 0) base = atomicAdd(a.sur_count, (unsigned int)__popcll(netm));
+      if (lane == 0) base = atomicAdd(a.sur_count + sl * kSurListStride, (unsigned int)__popcll(netm));
       base = __builtin_amdgcn_readfirstlane(base);
       const uint64_t slot = (uint64_t)base + (uint64_t)__popcll(netm & ((1ull << lane) - 1ull));
       if (net) {
-        if (slot < (uint64_t)a.sur_cap) a.sur_list[slot] = SurEntry{z, bnd, idx_nss};
+        if (slot < cap_l) a.sur_list[sl * cap_l + slot] = SurEntry{z, bnd, idx_nss};
         else net = false;
       }
     }
     const bool ex = in && !net;
-    const uint64_t exm = __ballot(ex);
-    if (exm && lane == 0) atomicAdd(m->ctr + 1, (unsigned long long)__popcll(exm));
+    n_exact += (unsigned int)__popcll(__ballot(ex));
     if (ex) acc += ma_loss<float>(z, bc);
   }
   return acc;
@@ -581,24 +599,48 @@ __device__ __forceinline__ float sur_loss_sum(const float* zb, int ns, int lane,
 // wave (every lane a network point), the loss from alpha_1 of the network
 // and the polynomials lambda_e = k^2, eta_d = k^2 (k^2 + 2 z^2)/2, taken off
 // the point's flux element (1/nss of it; elements with several listed
-// subsamples receive them in no fixed order).  Waves stride over the list;
-// the list length is read from the device.
+// subsamples receive them in no fixed order).  Lane l < kSurLists reads the
+// length of sub-list l; a wave-wide prefix sum of their 64-entry chunks
+// numbers the chunks of all sub-lists, and waves stride over those numbers.
+// The weight fragments of both layers are staged in LDS once per workgroup:
+// 128 KiB with the hi/lo split (one workgroup per compute unit), the 64 KiB
+// of hi parts without it (two).
 template <int SPLIT>
-__global__ __launch_bounds__(256) void k_sur_net(BatchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : 2, 8))) void k_sur_net(BatchArgs a) {
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const MlpDev* __restrict__ m = reinterpret_cast<const MlpDev*>(a.mlp);
+  constexpr int kStaged = (SPLIT ? 4 : 2) * kFragPerLayer;   // [layer][hi(, lo)]
+  extern __shared__ bf16x8 sfrag[];
+  const bf16x8* __restrict__ gf = &m->frag[0][0][0];
+  for (int i = threadIdx.x; i < kStaged; i += blockDim.x)
+    sfrag[i] = SPLIT ? gf[i] : gf[i < kFragPerLayer ? i : i + kFragPerLayer];
+  __syncthreads();
   float* __restrict__ flux = reinterpret_cast<float*>(a.flux);
-  const uint64_t n = min((uint64_t)*a.sur_count, (uint64_t)a.sur_cap);
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + wv) * kWave; base < n; base += waves * kWave) {
-    const uint64_t j = base + lane;
-    const bool ok = j < n;
+  const uint32_t cap_l = (uint32_t)(a.sur_cap / kSurLists);
+  static_assert(kSurLists == kWave, "one sub-list per lane");
+  const uint32_t cnt = min(a.sur_count[lane * kSurListStride], cap_l);
+  const uint32_t chunks = (cnt + kWave - 1) / kWave;
+  uint32_t incl = chunks;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  const uint32_t excl = incl - chunks;
+  const uint32_t total = __shfl(incl, kWave - 1);
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  unsigned int n_net = 0;
+  for (uint32_t t = blockIdx.x * (blockDim.x / kWave) + wv; t < total; t += waves) {
+    // the sub-list holding chunk t: lanes 0..l-1 end at or before it
+    const int l = __popcll(__ballot(incl <= t));
+    const uint32_t j = (t - (uint32_t)__shfl(excl, l)) * kWave + lane;
+    const bool ok = j < (uint32_t)__shfl(cnt, l);
     SurEntry e{0.5f, 0, 0};
-    if (ok) e = a.sur_list[j];
+    if (ok) e = a.sur_list[(uint64_t)l * cap_l + j];
     const BandConst bcv = a.bc[e.band];
     const float z = e.z, k = ok ? bcv.kf : 0.1f;
     float y1;
-    mlp_eval_wave<SPLIT, 1, 1>(m, &m->frag[0][0][0], z, k, lane, &y1);
+    mlp_eval_wave<SPLIT, 1, 1>(m, mlp_opaque_lds((const __attribute__((address_space(3))) bf16x8*)sfrag),
+                               SPLIT ? 2 * kFragPerLayer : kFragPerLayer, z, k, lane, &y1);
     if (ok) {
       const float k2 = k * k;
       const float loss = bcv.wf[0] * k2 + bcv.wf[1] * mlp_alpha1(z, k, y1) +
@@ -606,9 +648,9 @@ __global__ __launch_bounds__(256) void k_sur_net(BatchArgs a) {
       const int nss = (int)(e.idx_nss >> kSurNssShift);
       atomicAdd(flux + (e.idx_nss & ((1ull << kSurNssShift) - 1ull)), -loss / (float)nss);
     }
-    const uint64_t okm = __ballot(ok);
-    if (lane == 0) atomicAdd(m->ctr, (unsigned long long)__popcll(okm));
+    n_net += (unsigned int)__popcll(__ballot(ok));
   }
+  if (lane == 0 && n_net) atomicAdd(m->ctr, (unsigned long long)n_net);
 }
 
 // Bilinear interpolation of the three functions (Sect. 2.2.3); k outside the
@@ -729,7 +771,7 @@ __device__ __forceinline__ float interp_rows(const float* zb, int lane, const ch
 template <int PREC, int MODEL, class T>
 __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const BandConst* __restrict__ bc,
                                           int bnd, const BatchArgs& a, const T* __restrict__ tb,
-                                          uint64_t idx_nss, bool act_lane) {
+                                          uint64_t idx_nss, bool act_lane, unsigned int& n_exact) {
   static_assert(MODEL != kModelMAKhat || sizeof(T) == 4, "khat runs in the float path");
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   T acc = T(0);
@@ -787,7 +829,7 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
              bc->wf[2] * zb[(2 * kZChunk + s) * kWave + lane];
   } else if (MODEL == kModelMA) {
     if constexpr (SUR) {
-      acc = sur_loss_sum(zb, ns, lane, bc, bnd, a, idx_nss, act_lane);
+      acc = sur_loss_sum(zb, ns, lane, bc, bnd, a, idx_nss, act_lane, n_exact);
     } else {
       for (int s = 0; s < ns; ++s) acc += ma_loss<T>(zb[s * kWave + lane], bc);
     }
@@ -824,6 +866,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
   // have: every wave ends after at most its tiles + kQueues pops.
   int q = (int)(blockIdx.x % kQueues);
   int dry = 0;
+  unsigned int n_exact = 0;   // surrogate: exact in-transit points of this wave
   auto pop = [&](int qq) {
     unsigned int pos = 0;
     if (lane == 0) pos = atomicAdd(a.queue + qq * kQueueStride, 1u);
@@ -967,14 +1010,29 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         for (int bnd = b0; bnd < b1; ++bnd) finish(T(0), load_uniform(a.bc + bnd), bnd, i, act_lane);
         continue;
       }
-      if (nss <= kZChunk) {
+      if (F32 && MODEL == kModelMA && !SUR && !LOGL && nss <= kZChunk) {
+        // the float Mandel-Agol path: one orbit solve per (exposure,
+        // subsample), then per band only the leading 32 bytes of its
+        // constants (one scalar load instead of three: 0.564 -> 0.545 ms on
+        // the spectrophotometric batch; loading the next band's before the
+        // current band's model was slower, 0.585 ms, its wait shared with the
+        // LDS reads of z)
+        orbit_chunk(tm, dmid, 0, nss, true);
+        for (int bnd = b0; bnd < b1; ++bnd) {
+          const BandMAView cur = load_uniform(reinterpret_cast<const BandMAView*>(a.bc + bnd));
+          float acc = 0.0f;
+          for (int s = 0; s < nss; ++s) acc += ma_loss_view(zb[s * kWave + lane], cur);
+          const float f = cur.w0 == cur.w0 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
+          if (act_lane) flux[fo + (int64_t)(bnd - b0) * cnt + i] = f;
+        }
+      } else if (nss <= kZChunk) {
         // one orbit solve per (exposure, subsample), shared by every band
         orbit_chunk(tm, dmid, 0, nss, true);
         for (int bnd = b0; bnd < b1; ++bnd) {
           // band constants once per band, by scalar loads
           const BandConst bcv = load_uniform(a.bc + bnd);
           finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
-                                            sur_idx(bnd, i), act_lane),
+                                            sur_idx(bnd, i), act_lane, n_exact),
                  bcv, bnd, i, act_lane);
         }
       } else {
@@ -986,7 +1044,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
             const int ns = nss - s0 < kZChunk ? nss - s0 : kZChunk;
             orbit_chunk(tm, dmid, s0, ns, false);
             acc += band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
-                                              sur_idx(bnd, i), act_lane);
+                                              sur_idx(bnd, i), act_lane, n_exact);
           }
           finish(acc, bcv, bnd, i, act_lane);
         }
@@ -996,6 +1054,9 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
       for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off);
       if (lane == 0) a.partial[tid] = r2;
     }
+  }
+  if constexpr (SUR) {
+    if (lane == 0 && n_exact) atomicAdd(reinterpret_cast<const MlpDev*>(a.mlp)->ctr + 1, (unsigned long long)n_exact);
   }
 }
 
@@ -1016,7 +1077,16 @@ size_t batch_lds_bytes(int prec, int model) {
   return (size_t)(kBlock / kWave) * kZChunk * kWave * (prec == kPrecFP64 ? 8 : 4) * (model == kModelMAKhat ? 3 : 1);
 }
 
-hipError_t prepare_batch_kernels() { return hipSuccess; }
+constexpr int kSurNetLdsSplit = 4 * kFragPerLayer * (int)sizeof(bf16x8);   // 128 KiB
+
+hipError_t prepare_batch_kernels() {
+  const void* fns[2] = {(const void*)k_sur_net<1>, (const void*)k_sur_net<0>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kSurNetLdsSplit);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 // The flux-writing batch kernel for (prec, model), for occupancy queries.
 static const void* batch_kernel(int prec, int model) {
@@ -1094,12 +1164,12 @@ hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups,
     if (err != hipSuccess) return err;
   }
   if ((prec == kPrecSurrogate || prec == kPrecSurrogateBf16) && a.sur_cap > 0) {
-    // the network over the points the first pass left to it (sur_grid
-    // workgroups, a few per compute unit)
+    // the network over the points the first pass left to it: one workgroup
+    // per compute unit with the split (sur_grid), two without
     if (prec == kPrecSurrogate)
-      hipLaunchKernelGGL(k_sur_net<1>, dim3(a.sur_grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(k_sur_net<1>, dim3(a.sur_grid), dim3(kBlock), kSurNetLdsSplit, s, a);
     else
-      hipLaunchKernelGGL(k_sur_net<0>, dim3(a.sur_grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(k_sur_net<0>, dim3(2 * a.sur_grid), dim3(kBlock), kSurNetLdsSplit / 2, s, a);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
   }

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_mlp_errmap(MlpDev* __restrict__ m) {
   const float sc = (ci + (lane % 8) / 7.0f) / kTrustNC;
   const float z = fminf(sc, 0.9999999f) * (1.0f - k);
   float y1;
-  mlp_eval_wave<SPLIT, 1, 1>(m, &m->frag[0][0][0], z, k, lane, &y1);
+  mlp_eval_wave_global<SPLIT, 1, 1>(m, z, k, lane, &y1);
   const MaAlpha<double> ex = ma_alpha_exact<double>((double)z, (double)k);
   const bool served = z < (1.0f - k) - m->band;
   float e = served ? (float)fabs((double)mlp_alpha1(z, k, y1) - ex.ld) : 0.0f;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev* __restrict__ m, 
     const int cell = in ? mlp_cell(m, z, k) : -1;
     const bool tr = cell >= 0 && 4.0f * m->err[cell] <= kSurrogateFluxTol;
     float y1 = 0.0f;
-    if (__any(tr)) mlp_eval_wave<SPLIT, 1, 1>(m, &m->frag[0][0][0], z, k, lane, &y1);   // wave-uniform
+    if (__any(tr)) mlp_eval_wave_global<SPLIT, 1, 1>(m, z, k, lane, &y1);   // wave-uniform
     double a0 = 0, a1 = 0, a2 = 0;
     if (tr) {
       const double k2 = (double)k * k;
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpDev* __restrict__ m,
     const bool ok = i < n;
     const float z = ok ? zk[2 * i] : 0.5f, k = ok ? zk[2 * i + 1] : 0.1f;
     float y[3];
-    mlp_eval_wave<SPLIT, 0, 3>(m, &m->frag[0][0][0], z, k, lane, y);
+    mlp_eval_wave_global<SPLIT, 0, 3>(m, z, k, lane, y);
     if (ok) { out[3 * i] = y[0]; out[3 * i + 1] = y[1]; out[3 * i + 2] = y[2]; }
   }
 }
@@ -528,6 +528,12 @@ pt_status pt_surrogate_set(const pt_mlp* w, double fallback_band, double k_lo, d
   st.band = (float)fallback_band;
   st.k_lo = (float)k_lo;
   st.k_hi = (float)k_hi;
+  // hi/lo split of weights and activations (three bf16 products, ~16-bit
+  // operands); PT_MLP_SPLIT=0 keeps one bf16 product.  With one product the
+  // network's output carries the bf16 rounding of 128 activations per layer,
+  // which varies from point to point faster than the error map's grid
+  // resolves (a point between grid points measured 2x its cell's bound), so
+  // the split is the default.
   const char* sp = getenv("PT_MLP_SPLIT");
   st.split = (sp && sp[0] == '0') ? 0 : 1;
   hipLaunchKernelGGL(k_mlp_pack, dim3(grid1(2 * kFragPerLayer)), dim3(256), 0, s, *w, st.dev_ptr);

@@ -198,7 +198,7 @@ struct Plan {
   std::vector<int32_t> nss, band_off;
   DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, gtab64, queue, khat, ztab,
       ltab, sur;
-  int64_t sur_cap = 0;   // surrogate: list entries (sur holds a 256-byte counter line, then the list)
+  int64_t sur_cap = 0;   // surrogate: list entries (sur holds the sub-list counters, then the list)
   std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
   LaunchShape shape;
   bool tuned = false;
@@ -215,6 +215,7 @@ struct Plan {
 };
 
 static std::map<std::string, std::unique_ptr<Plan>> g_plans;
+constexpr size_t kSurHead = (size_t)kSurLists * kSurListStride * sizeof(unsigned int);   // counter lines
 
 static void hash_bytes(std::string& key, const void* p, size_t n) {
   // FNV-1a over the contents, appended as hex; plus the length
@@ -444,12 +445,15 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   PT_HIP(hipMemset(p->queue.p, 0, kQueues * kQueueStride * sizeof(unsigned int)));
   if (model == PT_MODEL_MA_KHAT) PT_HIP(p->khat.ensure(std::max<size_t>(1, n) * 8));
   if (prec == PT_PREC_SURROGATE) {
-    // every (subsample, exposure, band) point may be left to the network, up
-    // to kSurListMax per call (the rest take the float path)
+    // every (subsample, exposure, band) point may be left to the network;
+    // room for all of them and half again (the sub-lists fill unevenly), up
+    // to kSurListMax per call (points finding their sub-list full take the
+    // float path)
     int64_t pts = 0;
     for (size_t i = 0; i < n; ++i) pts += (int64_t)(b->band_off[i + 1] - b->band_off[i]) * b->t_count[i] * b->nss[i];
-    p->sur_cap = std::max<int64_t>(64, std::min<int64_t>(pts, kSurListMax));
-    PT_HIP(p->sur.ensure(256 + (size_t)p->sur_cap * sizeof(SurEntry)));
+    const int64_t unit = (int64_t)kSurLists * 64;
+    p->sur_cap = (std::min<int64_t>(std::max<int64_t>(pts + pts / 2, 1), kSurListMax) + unit - 1) / unit * unit;
+    PT_HIP(p->sur.ensure(kSurHead + (size_t)p->sur_cap * sizeof(SurEntry)));
   }
   if (model == PT_MODEL_GIMENEZ || model == PT_MODEL_GIMENEZ_ZINTERP) {
     const size_t nb = std::max<size_t>(1, (size_t)p->n_band);
@@ -509,9 +513,9 @@ static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, B
     a->mlp = surrogate_device_ptr(p->dev);
     if (!obs) {   // the likelihood path evaluates every point in its own pass
       a->sur_count = (unsigned int*)p->sur.p;
-      a->sur_list = (SurEntry*)((char*)p->sur.p + 256);
+      a->sur_list = (SurEntry*)((char*)p->sur.p + kSurHead);
       a->sur_cap = p->sur_cap;
-      a->sur_grid = 2 * std::max(1, cu_count());
+      a->sur_grid = std::max(1, cu_count());
     }
   }
   if (p->model == PT_MODEL_MA_KHAT) a->khat = (double*)p->khat.p;
