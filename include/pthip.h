@@ -20,8 +20,9 @@
  *  - Kernels never trap.  Non-physical values that cannot be checked on the
  *    host (device-resident parameters: e >= 1, aR <= 0, P <= 0, b < 0 or an
  *    inclination with cos i > 1) give NaN flux for the light curves they
- *    belong to, and a radius ratio that is not positive and finite gives
- *    NaN flux for its passband; NaN inputs give NaN outputs.
+ *    belong to, and a radius ratio that is not positive and finite, or
+ *    limb-darkening coefficients whose flux weights are not finite, give NaN
+ *    flux for their passband; NaN inputs give NaN outputs.
  *  - z < 0 marks the planet behind the star; its flux is 1.
  *  - Calls on different streams may run concurrently; the library's own
  *    caches are guarded by a mutex.
@@ -173,7 +174,8 @@ typedef struct {
  * rigorous truncation bound keeps z within 3e-8 (4..16 subsamples; otherwise
  * one solve per subsample); PT_PREC_FP64 solves per subsample.  A light curve
  * with non-physical orbit parameters, or a band with a radius ratio that is
- * not positive and finite, gives NaN in every affected output point.
+ * not positive and finite or with non-finite limb-darkening weights, gives
+ * NaN in every affected output point.
  *   flux    output [n_flux], device: float for PT_PREC_FP32/PT_PREC_SURROGATE,
  *           double for PT_PREC_FP64
  *   npol    Jacobi terms for PT_MODEL_GIMENEZ (1..512), ignored otherwise

@@ -197,3 +197,47 @@ def test_batch_surrogate_parity_and_network_share(pt):
     say("long-cadence: network points", net2, "exact", exact2)
     assert np.abs(got2 - O.lc_batch(b2, model=0)).max() <= 1e-5
     assert net2 > 0
+
+
+def test_batch_surrogate_ragged_edge_cases(pt):
+    """The two-pass surrogate path on a ragged batch: light curves with more
+    subsamples than one LDS chunk (the per-band orbit branch, several listed
+    subsamples per flux element), k above the network's range and above 1/2,
+    a planet larger than the star, an empty light curve and one without
+    bands, against the oracle; and NaN throughout for an invalid band and an
+    invalid orbit."""
+    from oracle import oracle as O
+    from paper_1504_07433_amd import workloads as W
+    _installed(pt)
+    b = W.config4(n_lc=10, n_min=20, n_max=300, max_nss=3, max_bands=3)
+    b["nss"][1] = 20
+    b["nss"][2] = 37
+    for i in range(len(b["t_start"])):          # times across the transit at t0 = 0
+        s0, c = b["t_start"][i], b["t_count"][i]
+        b["t"][s0:s0 + c] = np.linspace(-0.07, 0.07, c)
+    b["k"][b["band_off"][3]] = 0.7
+    b["k"][b["band_off"][4]] = 1.4
+    b["t_count"][5] = 0
+    b["band_off"][7:] -= (b["band_off"][7] - b["band_off"][6])
+    b["band_off"][6] = b["band_off"][7]
+    nb = np.diff(b["band_off"]).astype(np.int64)
+    sizes = nb * b["t_count"]
+    b["flux_off"] = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    b["n_flux"] = int(sizes.sum())
+    b["k"] = b["k"][:b["band_off"][-1]].copy()
+    b["u"] = b["u"][:b["band_off"][-1]].copy()
+    ref = O.lc_batch(b, model=0)
+    assert np.count_nonzero(ref < 1.0) > len(ref) // 4       # the transits are sampled
+    pt.surrogate_counters(reset=True)
+    got = pt.lc_batch(pt.DeviceBatch(b), "ma", prec="surrogate").cpu().numpy().astype(np.float64)
+    net, exact = pt.surrogate_counters(reset=True)
+    say("ragged surrogate: max|dF|", np.abs(got - ref).max(), "network", net, "exact", exact)
+    assert np.abs(got - ref).max() <= 1e-5
+    assert net > 0
+    # an invalid band (k = NaN) and an invalid orbit (e = 1.5): NaN in every exposure
+    b["k"][b["band_off"][0]] = np.nan
+    b["e"][2] = 1.5
+    got = pt.lc_batch(pt.DeviceBatch(b), "ma", prec="surrogate").cpu().numpy()
+    blk0 = got[b["flux_off"][0]:b["flux_off"][0] + b["t_count"][0]]
+    blk2 = got[b["flux_off"][2]:b["flux_off"][2] + nb[2] * b["t_count"][2]]
+    assert np.all(np.isnan(blk0)) and np.all(np.isnan(blk2))

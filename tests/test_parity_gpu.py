@@ -209,6 +209,9 @@ def test_batch_edge_cases(pt, O):
     b = W.config4(n_lc=10, n_min=20, n_max=300, max_nss=3, max_bands=3)
     b["nss"][1] = 20                         # more subsamples than one LDS chunk
     b["nss"][2] = 37
+    for i in range(len(b["t_start"])):          # times across the transit at t0 = 0
+        s0, c = b["t_start"][i], b["t_count"][i]
+        b["t"][s0:s0 + c] = np.linspace(-0.07, 0.07, c)
     b["k"][b["band_off"][3]] = 0.7           # k > 1/2: exact path in the float kernel
     b["k"][b["band_off"][4]] = 1.4           # planet larger than the star
     # an empty light curve and one without bands
@@ -222,6 +225,7 @@ def test_batch_edge_cases(pt, O):
     b["k"] = b["k"][:b["band_off"][-1]].copy()
     b["u"] = b["u"][:b["band_off"][-1]].copy()
     ref = O.lc_batch(b, model=0)
+    assert np.count_nonzero(ref < 1.0) > len(ref) // 4       # the transits are sampled
     for prec, tol in (("fp32", TOL32), ("fp64", TOL64)):
         g = _run(pt, b, "ma", prec)
         assert np.abs(g - ref).max() <= tol, prec
@@ -296,6 +300,14 @@ def test_batch_nonphysical_parameters_give_nan(pt):
         blk = lambda i: g[b["flux_off"][i]:b["flux_off"][i] + b["t_count"][i]]
         assert np.all(np.isnan(blk(1))) and np.all(np.isnan(blk(2))) and np.all(np.isnan(blk(3))), prec
         assert np.all(np.isfinite(blk(0))), prec
+    # limb-darkening coefficients with non-finite weights: an invalid band too
+    b2 = W.config2(n_vec=3, n_windows=1)
+    b2["u"][1, 0] = np.nan
+    for prec in ("fp32", "fp64"):
+        g2 = _run(pt, b2, "ma", prec)
+        s1 = slice(b2["flux_off"][1], b2["flux_off"][1] + b2["t_count"][1])
+        assert np.all(np.isnan(g2[s1])), prec
+        assert np.all(np.isfinite(g2[:b2["flux_off"][1]])) and np.all(np.isfinite(g2[s1.stop:])), prec
     b["k"][3] = -0.1
     g = _run(pt, b, "ma", "fp32")
     assert np.all(np.isnan(g[b["flux_off"][3]:b["flux_off"][3] + b["t_count"][3]]))
