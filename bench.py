@@ -82,11 +82,13 @@ NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 # launch, FETCH_SIZE and WRITE_SIZE in KiB per launch.  HBM bytes = FETCH_SIZE
 # x FETCH_SCALE + WRITE_SIZE x WRITE_SCALE, the factors being what the same
 # counters read for an elementwise kernel that reads and writes 1 GiB
-# (FETCH_SIZE 524319 KiB for 1 GiB read, WRITE_SIZE 1048580 KiB written).
+# (FETCH_SIZE 524309.7 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB written).
 COUNTERS = {
-    "long-cadence": {"valu_insts": 8.71723e8, "fetch_kib": 10920.7, "write_kib": 204912.0},
+    "spectrophotometric": {"valu_insts": 2.14824e8, "fetch_kib": 68628.4, "write_kib": 410486.0},
+    "long-cadence": {"valu_insts": 8.76792e8, "fetch_kib": 19888.8, "write_kib": 207529.0},
+    "uneven": {"valu_insts": 7.55599e9, "fetch_kib": 391981.0, "write_kib": 2839190.0},
 }
-FETCH_SCALE, WRITE_SCALE = 1048576 / 524319, 1.0
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524309.7, 1.0
 
 
 def parse():
