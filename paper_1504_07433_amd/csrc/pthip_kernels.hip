@@ -437,15 +437,18 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
   for (int64_t lc = wave; lc < a.n_lc; lc += n_waves) {
     const int b0 = a.band_off[lc], b1 = a.band_off[lc + 1];
     double kmax = 0.0, ks = 0.0;
+    bool ok = true;   // the band constants (formed by k_batch_prep) all valid
     for (int bnd = b0 + lane; bnd < b1; bnd += kWave) {
       kmax = fmax(kmax, a.k[bnd]);
       ks += a.k[bnd];
+      ok = ok && a.bc[bnd].valid != 0;
     }
     for (int off = 32; off > 0; off >>= 1) {
       kmax = fmax(kmax, __shfl_xor(kmax, off));
       ks += __shfl_xor(ks, off);
     }
     OrbitConst o = orbit_const(a.t0[lc], a.P[lc], a.aR[lc], a.b[lc], a.e[lc], a.w[lc], kmax);
+    o.bands_ok = __all(ok) ? 1 : 0;
     if (o.valid && o.dm_cut < kPi) {
       const double C = o.dm_cut;
       const double L = o.aR * sqrt((1.0 + o.e) / (1.0 - o.e)) * (1.0 + 1e-9);
@@ -879,6 +882,9 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
     constexpr bool F32 = sizeof(T) == 4;
     const int nss = a.nss[lc];
     const int b0 = a.band_off[lc], b1 = a.band_off[lc + 1];
+    // the tile's bands: all of the light curve's, or a run of them
+    const int bb = b0 + (td.bands & 0xffff);
+    const int be = td.bands ? bb + (td.bands >> 16) : b1;
     const int64_t cnt = a.t_count[lc];
     const double* __restrict__ tl = a.t + a.t_start[lc];
     const double texp = a.t_exp[lc];
@@ -906,6 +912,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
       oc = load_uniform(a.oc + lc);
     }
     const bool orbit_ok = F32 ? of.valid != 0 : oc.valid != 0;
+    const bool bands_ok = F32 ? of.bands_ok != 0 : oc.bands_ok != 0;
 
     // Mean-anomaly offset of the exposure centre, in double, and half the
     // exposure's span of subsample offsets plus a margin for the float
@@ -1006,8 +1013,14 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
       const double dmid = centre_dm(tm);
       const bool lane_out = !act_lane || dmid + half_dm < cut_lo || dmid - half_dm > cut_hi;
       if (orbit_ok && __all(lane_out)) {
-        // the whole wave is out of transit: the loss is 0 in every band
-        for (int bnd = b0; bnd < b1; ++bnd) finish(T(0), load_uniform(a.bc + bnd), bnd, i, act_lane);
+        // the whole wave is out of transit: the loss is 0 in every band, and
+        // with every band valid the flux is 1 without reading the bands
+        if (!LOGL && bands_ok) {
+          if (act_lane)
+            for (int bnd = bb; bnd < be; ++bnd) flux[fo + (int64_t)(bnd - b0) * cnt + i] = T(1);
+        } else {
+          for (int bnd = bb; bnd < be; ++bnd) finish(T(0), load_uniform(a.bc + bnd), bnd, i, act_lane);
+        }
         continue;
       }
       if (F32 && MODEL == kModelMA && !SUR && !LOGL && nss <= kZChunk) {
@@ -1018,17 +1031,26 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         // current band's model was slower, 0.585 ms, its wait shared with the
         // LDS reads of z)
         orbit_chunk(tm, dmid, 0, nss, true);
-        for (int bnd = b0; bnd < b1; ++bnd) {
-          const BandMAView cur = load_uniform(reinterpret_cast<const BandMAView*>(a.bc + bnd));
-          float acc = 0.0f;
-          for (int s = 0; s < nss; ++s) acc += ma_loss_view(zb[s * kWave + lane], cur);
-          const float f = cur.w0 == cur.w0 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
-          if (act_lane) flux[fo + (int64_t)(bnd - b0) * cnt + i] = f;
-        }
+        // without supersampling z stays in a register across the bands
+        auto band_loop = [&](auto one) {
+          constexpr bool ONE = decltype(one)::value;
+          const float z1 = ONE ? zb[lane] : 0.0f;
+          for (int bnd = bb; bnd < be; ++bnd) {
+            const BandMAView cur = load_uniform(reinterpret_cast<const BandMAView*>(a.bc + bnd));
+            float acc = 0.0f;
+            if (ONE) acc = ma_loss_view(z1, cur);
+            else
+              for (int s = 0; s < nss; ++s) acc += ma_loss_view(zb[s * kWave + lane], cur);
+            const float f = cur.w0 == cur.w0 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
+            if (act_lane) flux[fo + (int64_t)(bnd - b0) * cnt + i] = f;
+          }
+        };
+        if (nss == 1) band_loop(std::true_type());
+        else band_loop(std::false_type());
       } else if (nss <= kZChunk) {
         // one orbit solve per (exposure, subsample), shared by every band
         orbit_chunk(tm, dmid, 0, nss, true);
-        for (int bnd = b0; bnd < b1; ++bnd) {
+        for (int bnd = bb; bnd < be; ++bnd) {
           // band constants once per band, by scalar loads
           const BandConst bcv = load_uniform(a.bc + bnd);
           finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
@@ -1037,7 +1059,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         }
       } else {
         // more subsamples than one LDS chunk: the orbit is solved per band
-        for (int bnd = b0; bnd < b1; ++bnd) {
+        for (int bnd = bb; bnd < be; ++bnd) {
           const BandConst bcv = load_uniform(a.bc + bnd);
           T acc = T(0);
           for (int s0 = 0; s0 < nss; s0 += kZChunk) {

@@ -199,7 +199,7 @@ struct Plan {
   DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, gtab64, queue, khat, ztab,
       ltab, sur;
   int64_t sur_cap = 0;   // surrogate: list entries (sur holds the sub-list counters, then the list)
-  std::map<int, std::unique_ptr<TileSet>> tilesets;  // by tile size
+  std::map<std::pair<int, int64_t>, std::unique_ptr<TileSet>> tilesets;  // by tile size and split tail
   LaunchShape shape;
   bool tuned = false;
   // captured graphs for the last argument set: [0] flux, [1] likelihood
@@ -299,14 +299,18 @@ static pt_status validate_batch(const pt_batch* b, pt_model model, int32_t npol,
   return PT_OK;
 }
 
-static pt_status build_tiles(Plan* p, int tile_e, TileSet** out) {
-  auto it = p->tilesets.find(tile_e);
+// The tile list for tile size tile_e and a grid of `workgroups`: its last
+// kTileTailWaves tiles per wave of the grid split into small pieces.
+static pt_status build_tiles(Plan* p, int tile_e, int workgroups, TileSet** out) {
+  const int64_t tail = (int64_t)kTileTailWaves * workgroups * (kBlock / kWave);
+  const auto key = std::make_pair(tile_e, tail);
+  auto it = p->tilesets.find(key);
   if (it != p->tilesets.end()) {
     *out = it->second.get();
     return PT_OK;
   }
   TilePlan tp;
-  make_tile_plan(p->n_lc, p->t_count.data(), p->nss.data(), p->band_off.data(), tile_e, &tp);
+  make_tile_plan(p->n_lc, p->t_count.data(), p->nss.data(), p->band_off.data(), tile_e, tail, &tp);
   if (tp.tiles.size() > 0x7fffffffu) return fail(PT_ERR_ARG, "more than 2^31 tiles; use larger tiles");
   auto ts = std::make_unique<TileSet>();
   ts->n_tiles = (int64_t)tp.tiles.size();
@@ -320,7 +324,7 @@ static pt_status build_tiles(Plan* p, int tile_e, TileSet** out) {
   if (!tp.lc_tiles.empty())
     PT_HIP(hipMemcpy(ts->lc_tiles.p, tp.lc_tiles.data(), tp.lc_tiles.size() * 4, hipMemcpyHostToDevice));
   *out = ts.get();
-  p->tilesets[tile_e] = std::move(ts);
+  p->tilesets[key] = std::move(ts);
   return PT_OK;
 }
 
@@ -475,10 +479,10 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   return PT_OK;
 }
 
-static pt_status fill_args(const pt_batch* b, Plan* p, int tile_e, void* flux, BatchArgs* a,
+static pt_status fill_args(const pt_batch* b, Plan* p, const LaunchShape& shape, void* flux, BatchArgs* a,
                            const void* obs = nullptr, const double* sigma = nullptr, double* loglike = nullptr) {
   TileSet* ts = nullptr;
-  pt_status st = build_tiles(p, tile_e, &ts);
+  pt_status st = build_tiles(p, shape.tile_e, shape.workgroups, &ts);
   if (st != PT_OK) return st;
   memset(a, 0, sizeof *a);
   a->t = b->t; a->t0 = b->t0; a->P = b->P; a->aR = b->aR; a->b = b->b; a->e = b->e; a->w = b->w;
@@ -774,7 +778,7 @@ pt_status pt_lc_batch(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   st = get_plan(batch, model, npol, prec, (hipStream_t)stream, &p, nullptr);
   if (st != PT_OK) return st;
   BatchArgs a;
-  st = fill_args(batch, p, p->shape.tile_e, flux, &a);
+  st = fill_args(batch, p, p->shape, flux, &a);
   if (st != PT_OK) return st;
   st = run_plan(p, a, p->shape.workgroups, (hipStream_t)stream);
   if (st != PT_OK) return st;
@@ -835,7 +839,7 @@ pt_status pt_lc_loglike(const pt_batch* batch, pt_model model, int32_t npol, pt_
   if (st != PT_OK) return st;
   BatchArgs a;
   // a non-null obs pointer selects the likelihood kernels, even for n_flux = 0
-  st = fill_args(batch, p, p->shape.tile_e, nullptr, &a, obs ? obs : (const void*)sigma, sigma, loglike);
+  st = fill_args(batch, p, p->shape, nullptr, &a, obs ? obs : (const void*)sigma, sigma, loglike);
   if (st != PT_OK) return st;
   st = run_plan(p, a, p->shape.workgroups, (hipStream_t)stream);
   if (st != PT_OK) return st;
@@ -903,7 +907,7 @@ pt_status pt_autotune(const pt_batch* batch, pt_model model, int32_t npol, pt_pr
   for (size_t ci = 0; ci < cand.size() && st == PT_OK; ++ci) {
     const LaunchShape& c = cand[ci];
     BatchArgs a;
-    st = fill_args(batch, p, c.tile_e, flux, &a);
+    st = fill_args(batch, p, c, flux, &a);
     if (st != PT_OK) break;
     if (a.n_tiles == 0) continue;
     if (ci > 0 && (int64_t)c.workgroups * (kBlock / kWave) > 4 * a.n_tiles) continue;   // mostly idle waves

@@ -348,6 +348,8 @@ struct OrbitConst {
   double dm_cut;          // |dM| beyond this: certainly out of transit
   double cut_lo, cut_hi;  // dM outside [cut_lo, cut_hi]: certainly out of transit
   int32_t circular, valid;
+  int32_t bands_ok;       // every band of the light curve valid (set with the window)
+  int32_t pad;
 };
 
 // b is the transit impact parameter a cos i (1-e^2)/(1+e sin w) / R*; t0 the
@@ -377,6 +379,8 @@ PT_HD OrbitConst orbit_const(double t0, double P, double aR, double b, double e,
   o.a2 = -b2;
   o.a3 = 2.0 * b2 * b2 - b3;
   o.circular = (e == 0.0) ? 1 : 0;
+  o.bands_ok = 0;
+  o.pad = 0;
   // Out-of-transit bound: in transit needs |f - f_c| < asin((1+k)/(aR(1-e)))
   // (projected distance >= r |cos(w+f)| >= a(1-e)|sin(f-f_c)|, and the planet
   // is behind the star beyond pi/2), and |dM| <= max(dM/df) |f - f_c| with
@@ -485,6 +489,7 @@ struct OrbitF {
   float cut_lo, cut_hi;   // in-transit window of dM (float, widened)
   int32_t circular, valid;
   int32_t series;         // order of the per-exposure position series, 0: one solve per subsample
+  int32_t bands_ok;       // every band of the light curve valid
 };
 
 PT_HD OrbitF orbit_f(const OrbitConst& o) {
@@ -514,6 +519,7 @@ PT_HD OrbitF orbit_f(const OrbitConst& o) {
   f.circular = o.circular;
   f.valid = o.valid;
   f.series = 0;
+  f.bands_ok = o.bands_ok;
   return f;
 }
 

@@ -4,6 +4,7 @@
 // next_tile the kernel runs, with a plain counter in place of the atomic), the
 // per-tile partial sums of the likelihood and their per-light-curve reduction
 // in tile-list order.
+#include <algorithm>
 #include <cstring>
 #include <random>
 
@@ -16,23 +17,57 @@ extern "C" {
 //   4 a wave popped more than (its tiles + kQueues) times, 5 a light curve's
 //   tile list holds another light curve's tile or misses one of its own,
 //   6 a reduced sum differs from the direct sum over the light curve's tiles,
-//   7 a tile's exposures leave its light curve, 8 tiles not in work order.
-// stats[0] = tiles, stats[1] = pops, stats[2] = largest pops of one wave.
+//   7 a tile's exposures or bands leave its light curve, 8 tiles not in work
+//   order (the whole tiles, then the pieces of the split tail, each longest
+//   first), 9 an (exposure, band) element of a light curve in no tile or in
+//   two, 10 a tail tile of a light curve with enough bands left whole, split
+//   into too few bands, or a tile before the tail split.
+// tail: tiles split at the end of the order (make_tile_plan).
+// stats[0] = tiles, stats[1] = pops, stats[2] = largest pops of one wave,
+// stats[3] = tiles that are pieces of the split tail.
 int queue_check(int32_t n_lc, const int64_t* t_count, const int32_t* nss, const int32_t* band_off, int tile_e,
-                int n_workgroups, int waves_per_group, unsigned seed, int64_t* stats) {
+                int64_t tail, int n_workgroups, int waves_per_group, unsigned seed, int64_t* stats) {
   pt::TilePlan tp;
-  pt::make_tile_plan(n_lc, t_count, nss, band_off, tile_e, &tp);
+  pt::make_tile_plan(n_lc, t_count, nss, band_off, tile_e, tail, &tp);
   const int64_t n_tiles = (int64_t)tp.tiles.size();
+  auto nb_of = [&](const pt::TileDesc& t) {
+    return t.bands ? t.bands >> 16 : band_off[t.lc + 1] - band_off[t.lc];
+  };
+  // the whole tiles come first: those of the plan without a tail, less the
+  // `tail` it splits
+  pt::TilePlan whole;
+  pt::make_tile_plan(n_lc, t_count, nss, band_off, tile_e, 0, &whole);
+  const int64_t n_whole = (int64_t)whole.tiles.size();
+  const int64_t n_split = tail > 0 ? std::min<int64_t>(tail, n_whole) : 0;
+  const int64_t head = n_whole - n_split;
+  std::vector<std::vector<uint8_t>> cover(n_lc);
+  for (int32_t lc = 0; lc < n_lc; ++lc)
+    cover[lc].assign((size_t)t_count[lc] * (size_t)(band_off[lc + 1] - band_off[lc]), 0);
   for (int64_t j = 0; j < n_tiles; ++j) {
     const pt::TileDesc& t = tp.tiles[j];
     if (t.lc < 0 || t.lc >= n_lc || t.e0 < 0 || t.ne < 1 || t.e0 + t.ne > t_count[t.lc]) return 7;
-    if (j > 0) {
+    const int nb = band_off[t.lc + 1] - band_off[t.lc];
+    const int lo = t.bands & 0xffff, cnt = nb_of(t);
+    if (cnt < 1 || lo + cnt > nb) return 7;
+    for (int e = t.e0; e < t.e0 + t.ne; ++e)
+      for (int b = lo; b < lo + cnt; ++b)
+        if (cover[t.lc][(size_t)b * t_count[t.lc] + e]++) return 9;
+    if (j >= head) {
+      if (t.bands && cnt < pt::kTileSplitMinBands) return 10;
+      if (!t.bands && nb >= 2 * pt::kTileSplitMinBands && nb <= pt::kTileBandsMax) return 10;
+    } else if (t.bands) {
+      return 10;
+    }
+    if (j > 0 && j != head) {
       const pt::TileDesc& u = tp.tiles[j - 1];
-      const double wu = pt::tile_work(u.ne, nss[u.lc], band_off[u.lc + 1] - band_off[u.lc]);
-      const double wt = pt::tile_work(t.ne, nss[t.lc], band_off[t.lc + 1] - band_off[t.lc]);
+      const double wu = pt::tile_work(u.ne, nss[u.lc], nb_of(u));
+      const double wt = pt::tile_work(t.ne, nss[t.lc], cnt);
       if (wt > wu) return 8;
     }
   }
+  for (int32_t lc = 0; lc < n_lc; ++lc)
+    for (uint8_t c : cover[lc])
+      if (c != 1) return 9;
   // waves of the persistent grid: wave w belongs to workgroup w / waves_per_group
   const int n_waves = n_workgroups * waves_per_group;
   std::vector<unsigned int> counter(pt::kQueues, 0u);
@@ -90,6 +125,7 @@ int queue_check(int32_t n_lc, const int64_t* t_count, const int32_t* nss, const 
   stats[0] = n_tiles;
   stats[1] = total_pops;
   stats[2] = max_pops;
+  stats[3] = n_tiles - head;
   return 0;
 }
 
