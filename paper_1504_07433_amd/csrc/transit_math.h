@@ -120,13 +120,19 @@ template <> struct Num<double> {
   static constexpr int newton_max = 40;
 };
 
-// Double-precision arithmetic with approximate hardware seeds: the
-// reciprocal and square root start from v_rcp_f64 / v_rsq_f64 (relative error
-// ~5e-8, measured on gfx950) and take one Newton step in double, leaving
-// ~2e-15.  A double FMA issues at the rate of a float FMA on gfx950 (packed
-// float math aside), so this keeps the cancellation-prone elliptic
-// combinations at near-double accuracy for about the cost of the float
-// transcendentals.  (The host build seeds from float, for tolerance work.)
+// Double-precision arithmetic with approximate hardware seeds, for the
+// elliptic combination of the float path: v_rcp_f64 / v_rsq_f64 have a
+// relative error of ~5e-8 (measured on gfx950).  The reciprocal takes one
+// Newton step in double (~2e-15): it divides by |z - k| and by the mean's
+// p, and unrefined it moved the flux by up to 1.4e-6 near the limb for small
+// k.  The reciprocal square roots (modulus, prefactor) and the square roots
+// of the mean are left unrefined: at a seed error of 5e-8 the flux moves by
+// at most 1.6e-7 for any quadratic law (0.3x of that for typical ones), and
+// the two Newton steps and two to three square-root steps they save are
+// about 13 of the ~230 double instructions of a point.  A double FMA issues
+// at the rate of a float FMA on gfx950 (packed float math aside), so double
+// arithmetic here costs no more than float.  sqrt keeps its Newton step.
+// (The host build seeds from float, for tolerance work.)
 struct NumFast {
   PT_HD static double rcp(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -149,15 +155,12 @@ struct NumFast {
   }
   PT_HD static double rsqrt(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const double y = __builtin_amdgcn_rsq(x);
+    return __builtin_amdgcn_rsq(x);
 #else
-    const double y = (double)(1.0f / ::sqrtf((float)x));
+    return (double)(1.0f / ::sqrtf((float)x));
 #endif
-    const double r = fma(-x * y, y, 1.0);    // 1 - x y^2
-    return fma(0.5 * y, r, y);
   }
-  // 2 sqrt(x): the same Newton step scaled by two (bit for bit twice sqrt),
-  // one multiplication fewer than doubling the square root
+  // 2 sqrt(x) from the seed
   PT_HD static double sqrt2(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const double y = __builtin_amdgcn_rsq(x);
@@ -165,8 +168,7 @@ struct NumFast {
     const double y = (double)(1.0f / ::sqrtf((float)x));
 #endif
     const double s = x * y;
-    const double r = fma(-s, s, x);
-    return fma(y, r, s + s);
+    return s + s;
   }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) { Num<double>::sincos(x, s, c); }

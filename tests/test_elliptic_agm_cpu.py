@@ -90,7 +90,12 @@ def sample(lib):
     return z, k, _reference(lib, z, k)
 
 
-@pytest.mark.parametrize("fast,tol", [(0, 1e-13), (1, 5e-9)])
+# fast = 1: the float path's seeds (float here, ~5e-8 on gfx950) with the
+# square roots unrefined.  lambda_d enters the flux with weight c/N =
+# (u1 + 2 u2) / (1 - u1/3 - u2/6) <= 2.4 over the physical quadratic laws, so
+# 2e-7 here keeps the float path's flux within 4.8e-7 of the model (its
+# tolerance is 1e-6).
+@pytest.mark.parametrize("fast,tol", [(0, 1e-13), (1, 2e-7)])
 def test_combination_against_carlson(lib, sample, fast, tol):
     z, k, ref = sample
     got = np.empty(len(z))
