@@ -524,6 +524,15 @@ __device__ __forceinline__ float ma_loss<float>(float z, const BandConst* __rest
   return bc->wf[0] * r.le + bc->wf[1] * r.ld + bc->wf[2] * r.ed;
 }
 
+// The same for a band outside an interpolation table's k range, out of line
+// so that the tabulated path keeps its registers (and its occupancy).
+__device__ __noinline__ float ma_loss_outside_table(float z, float kf, double kd, int exact, float omk,
+                                                    float onepk, float w0, float w1, float w2) {
+  if (z < 0.0f || z >= onepk) return 0.0f;
+  const MaAlpha<float> r = ma_alpha_fast(z, kf, kd, exact, omk);
+  return w0 * r.le + w1 * r.ld + w2 * r.ed;
+}
+
 // The same from the leading part of the band's constants.
 __device__ __forceinline__ float ma_loss_view(float z, const BandMAView& v) {
   if (z < 0.0f || z >= v.onepk) return 0.0f;
@@ -815,7 +824,9 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
 #undef PT_ROWS_CASE
       }
     } else {
-      for (int s = 0; s < ns; ++s) acc += ma_loss<float>(zb[s * kWave + lane], bc);
+      for (int s = 0; s < ns; ++s)
+        acc += ma_loss_outside_table(zb[s * kWave + lane], bc->kf, bc->kd, bc->exact, bc->omk, bc->onepk,
+                                     bc->wf[0], bc->wf[1], bc->wf[2]);
     }
   } else if constexpr (MODEL == kModelGimenezZInterp) {
     // k >= 1 has no inner grid: direct series
@@ -1050,12 +1061,24 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
       } else if (nss <= kZChunk) {
         // one orbit solve per (exposure, subsample), shared by every band
         orbit_chunk(tm, dmid, 0, nss, true);
-        for (int bnd = bb; bnd < be; ++bnd) {
-          // band constants once per band, by scalar loads
-          const BandConst bcv = load_uniform(a.bc + bnd);
-          finish(band_loss_sum<PREC, MODEL>(zb, nss, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
-                                            sur_idx(bnd, i), act_lane, n_exact),
-                 bcv, bnd, i, act_lane);
+        // the float models without supersampling see a chunk length of one
+        // at compile time, so the read of z leaves the band loop
+        auto band_loop = [&](auto one) {
+          constexpr bool ONE = decltype(one)::value;
+          const int ns = ONE ? 1 : nss;
+          for (int bnd = bb; bnd < be; ++bnd) {
+            // band constants once per band, by scalar loads
+            const BandConst bcv = load_uniform(a.bc + bnd);
+            finish(band_loss_sum<PREC, MODEL>(zb, ns, lane, &bcv, bnd, a, gtab + bnd * tab_stride,
+                                              sur_idx(bnd, i), act_lane, n_exact),
+                   bcv, bnd, i, act_lane);
+          }
+        };
+        if constexpr (F32 && !SUR && !LOGL) {
+          if (nss == 1) band_loop(std::true_type());
+          else band_loop(std::false_type());
+        } else {
+          band_loop(std::false_type());
         }
       } else {
         // more subsamples than one LDS chunk: the orbit is solved per band
