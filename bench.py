@@ -86,7 +86,7 @@ NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 COUNTERS = {
     "spectrophotometric": {"valu_insts": 1.88468e8, "fetch_kib": 18839.4, "write_kib": 419919.0},
     "long-cadence": {"valu_insts": 8.13972e8, "fetch_kib": 10816.8, "write_kib": 204911.0},
-    "uneven": {"valu_insts": 7.55599e9, "fetch_kib": 391981.0, "write_kib": 2839190.0},
+    "uneven": {"valu_insts": 6.94268e9, "fetch_kib": 381527.0, "write_kib": 2845240.0},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524309.7, 1.0
 

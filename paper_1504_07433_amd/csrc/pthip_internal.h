@@ -96,14 +96,14 @@ struct BatchArgs {
   const TileDesc* tiles;
   OrbitConst* oc;       // [n_lc], written by the window kernel
   OrbitF* ocf;          // [n_lc] float form, written by the window kernel
-  BandConst* bc;        // [n_band], written by the prep kernel
+  BandConst* bc;        // [n_band], written by the window kernel
   void* gtab;           // Gimenez per-band folded Chebyshev rows [n_band][2][gim_fold_row(npol)]
                         // in the working type
   double* gtab64;       // the double Jacobi rows [n_band][nldc+1][gim_row(npol)] they come from
   const double* gconn;  // [nldc+1][row][row] Chebyshev coefficients of P_j^(0,nu+1)
   const double* gconnq; // [nldc+1][row][gim_fold_row] the same times ((1+x)/2)^q_n
   const double4* gbcoef;  // [(nldc+1)][npol] {A_j, B_j, C_j, A'_{n,j}} of the band tables
-  unsigned int* queue;  // kQueues counters, kQueueStride apart (reset by the prep kernel)
+  unsigned int* queue;  // kQueues counters, kQueueStride apart (reset by the window kernel)
   void* flux;
   int64_t n_tiles;
   int32_t n_lc;
@@ -114,7 +114,7 @@ struct BatchArgs {
   // surrogate
   const void* mlp;      // device MlpDev (bf16 weights) or null
   SurEntry* sur_list;   // points left to the network [sur_cap], kSurLists sub-lists
-  unsigned int* sur_count;  // entries appended per sub-list, kSurListStride apart (reset by the prep kernel)
+  unsigned int* sur_count;  // entries appended per sub-list, kSurListStride apart (reset by the window kernel)
   int64_t sur_cap;      // multiple of kSurLists * 64; 0: no list, every point takes the float path
   int32_t sur_grid;     // workgroups of the network pass
   // fused likelihood (obs == null: write flux)
@@ -127,7 +127,7 @@ struct BatchArgs {
   double* loglike;      // [n_lc]
   MaTable matab;        // kModelMAInterp
   float2* ltab;         // [n_band][matab.nz] (L_j, L_j+1): loss at the z nodes for the band's k
-  double* khat;         // [n_lc] mean radius ratio (kModelMAKhat), written by prep
+  double* khat;         // [n_lc] mean radius ratio (kModelMAKhat), written by the window kernel
   float* ztab;          // [n_band][zin + zlimb] loss at the z nodes (kModelGimenezZInterp)
   int32_t zin, zlimb;
 };
@@ -171,8 +171,8 @@ hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u,
                           int npol, const void* tab, const void* rec, int prec, double* flux,
                           hipStream_t s);
 
-// Prep (orbit and band constants, queue reset), Gimenez tables when needed,
-// and the persistent kernel on `workgroups` workgroups of kBlock threads.
+// The window kernel (orbit and band constants, queue reset), Gimenez tables
+// when needed, and the persistent kernel on `workgroups` workgroups of kBlock threads.
 hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups, hipStream_t s);
 // Dynamic LDS of the batch kernel; opt-in of the surrogate variants above 64 KiB.
 size_t batch_lds_bytes(int prec, int model);

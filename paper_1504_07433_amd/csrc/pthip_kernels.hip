@@ -6,8 +6,8 @@
 // k_gim_cheb         their Chebyshev rows for the float path (pt_gimenez)
 // k_gim_cheb_fold    per band, the float batch path's two folded rows
 // k_gimenez          Gimenez, one k, nb bands                   (Sect. 2.1)
-// k_batch_prep       per-band constants, queue reset
-// k_lc_window        per-light-curve orbit constants and in-transit window
+// k_lc_window        per-band constants, per-light-curve orbit constants and
+//                    in-transit window, queue reset
 // k_lc_batch         persistent fused orbit + flux + supersampling over a
 //                    ragged batch (Sects. 2.1.3, 2.2.2, 3.2)
 #include <type_traits>
@@ -408,14 +408,6 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
   return c;
 }
 
-__global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x < kQueues) a.queue[threadIdx.x * kQueueStride] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x < kSurLists && a.sur_count) a.sur_count[threadIdx.x * kSurListStride] = 0u;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_band; i += stride)
-    a.bc[i] = band_const(a.k[i], a.u + i * a.nldc, a.nldc, a.model);
-}
-
 // ---------------------------------------------------------------------------
 // Per-light-curve orbit constants and in-transit window, one wavefront per
 // light curve.  The window is the set of mean-anomaly offsets dM where
@@ -434,14 +426,25 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t n_waves = (int64_t)gridDim.x * blockDim.x / kWave;
+  // queue and surrogate-list counters of the batch kernel that follows
+  if (blockIdx.x == 0 && threadIdx.x < kQueues) a.queue[threadIdx.x * kQueueStride] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kSurLists && a.sur_count) a.sur_count[threadIdx.x * kSurListStride] = 0u;
+  // bands ahead of the first light curve's belong to none; their constants
+  // are formed too, for the per-band table kernels that run over all bands
+  if (a.n_lc > 0)
+    for (int64_t bnd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; bnd < a.band_off[0];
+         bnd += (int64_t)gridDim.x * blockDim.x)
+      a.bc[bnd] = band_const(a.k[bnd], a.u + bnd * a.nldc, a.nldc, a.model);
   for (int64_t lc = wave; lc < a.n_lc; lc += n_waves) {
     const int b0 = a.band_off[lc], b1 = a.band_off[lc + 1];
     double kmax = 0.0, ks = 0.0;
-    bool ok = true;   // the band constants (formed by k_batch_prep) all valid
+    bool ok = true;   // every band constant valid
     for (int bnd = b0 + lane; bnd < b1; bnd += kWave) {
-      kmax = fmax(kmax, a.k[bnd]);
-      ks += a.k[bnd];
-      ok = ok && a.bc[bnd].valid != 0;
+      const BandConst c = band_const(a.k[bnd], a.u + (int64_t)bnd * a.nldc, a.nldc, a.model);
+      a.bc[bnd] = c;
+      kmax = fmax(kmax, c.kd);
+      ks += c.kd;
+      ok = ok && c.valid != 0;
     }
     for (int off = 32; off > 0; off >>= 1) {
       kmax = fmax(kmax, __shfl_xor(kmax, off));
@@ -1178,11 +1181,8 @@ static void launch_main(const BatchArgs& a, int prec, int model, dim3 grid, size
 }
 
 hipError_t launch_batch(const BatchArgs& a, int prec, int model, int workgroups, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_prep, dim3(grid_for(a.n_band > 0 ? a.n_band : 1, 256)), dim3(256), 0, s, a);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_lc_window, dim3(grid_for((int64_t)a.n_lc * kWave, 256)), dim3(256), 0, s, a);
-  err = hipGetLastError();
+  hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (model == kModelGimenez || model == kModelGimenezZInterp) {
     // band tables in double, then each band's two folded Chebyshev rows in the working type

@@ -1138,7 +1138,7 @@ pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec pre
   a.oc = (OrbitConst*)(D.ptr + L.oc);
   a.ocf = (OrbitF*)(D.ptr + L.ocf);
   a.bc = (BandConst*)(D.ptr + L.bc);
-  a.queue = (unsigned int*)D.ptr;   // reset by the prep kernel
+  a.queue = (unsigned int*)D.ptr;   // reset by the window kernel
   a.flux = flux;
   a.n_lc = (int32_t)n_lc;
   a.n_band = (int32_t)n_band;
