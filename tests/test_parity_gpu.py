@@ -175,10 +175,11 @@ def test_batch_spectrophotometric_small(pt, O):
     assert np.abs(_run(pt, bs, "gimenez", "fp64", u=ug) - refg).max() <= 1e-12
 
 
-@pytest.mark.parametrize("npol,nldc", [(1, 1), (5, 3), (100, 4), (512, 2)])
+@pytest.mark.parametrize("npol,nldc", [(1, 1), (5, 3), (60, 4), (61, 2), (100, 4), (512, 2)])
 def test_batch_gimenez_orders_and_laws(pt, O, npol, nldc):
     """The batch's folded Chebyshev rows at small and large npol (rows of more
-    than one wavefront of coefficients, one to many Clenshaw blocks) and
+    than one wavefront of coefficients, one to many Clenshaw blocks; up to
+    npol = 60 formed in one pass with the band tables, from 61 in two) and
     general laws of 1..4 coefficients, FP32 and FP64, against the oracle."""
     from paper_1504_07433_amd import workloads as W
     b = W.config3(n_vec=3, n_band=6, n_exp=300)
@@ -235,6 +236,66 @@ def test_batch_edge_cases(pt, O):
     for prec, tol in (("fp32", TOL32), ("fp64", TOL64)):
         g = _run(pt, b, "gimenez", prec, npol=20, u=ug)
         assert np.abs(g - refg).max() <= tol, ("gimenez", prec)
+
+
+def _wide_batch(seed=11):
+    """Light curves with many bands (16, 17, 33, 64, 70) beside narrow ones,
+    ragged exposure counts around one wave (1, 63, 64, 65, ...), 1, 2, 3, 5 and
+    19 subsamples, times across the transit (the first and the last light
+    curve with whole waves outside the in-transit window): the tail of the
+    tile list splits the wide light curves' tiles into runs of bands."""
+    from paper_1504_07433_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    nb = np.array([64, 70, 17, 16, 15, 33, 1, 40, 64], np.int64)
+    cnt = np.array([130, 65, 63, 1, 200, 97, 64, 300, 190], np.int64)
+    nss = np.array([1, 1, 3, 1, 2, 19, 1, 5, 1], np.int32)
+    n = len(nb)
+    b = W._empty_batch(n)
+    b["t0"][:] = rng.uniform(-0.01, 0.01, n)
+    b["P"][:] = 3.0
+    b["aR"][:] = rng.uniform(8.0, 12.0, n)
+    b["b"][:] = rng.uniform(0.1, 0.6, n)
+    b["e"][:] = np.where(np.arange(n) % 3 == 0, 0.0, rng.uniform(0.0, 0.3, n))
+    b["w"][:] = rng.uniform(0, 2 * np.pi, n)
+    b["t_exp"][:] = 0.004
+    b["nss"][:] = nss
+    span = np.where((np.arange(n) == 0) | (np.arange(n) == n - 1), 0.25, 0.09)   # whole waves out of window
+    t = np.concatenate([np.linspace(-h, h, c) for h, c in zip(span, cnt)])
+    t_start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    k = rng.uniform(0.05, 0.15, int(nb.sum()))
+    u = np.stack([rng.uniform(0.1, 0.6, len(k)), rng.uniform(0.0, 0.3, len(k))], 1)
+    return W._finish(b, t, t_start, cnt, nb, k, u, "wide")
+
+
+def test_band_split_tiles_match_oracle(pt, O):
+    """Tiles split into runs of bands (and whole tiles of the narrow light
+    curves) against the oracle element by element, float and FP64; then one
+    invalid band in each of two wide light curves: NaN in that band only,
+    including its exposures outside the in-transit window, where a wave with
+    every band valid stores 1 without reading the band constants."""
+    b = _wide_batch()
+    ref = O.lc_batch(b, model=0)
+    assert np.count_nonzero(ref < 1.0) > len(ref) // 4
+    for prec, tol in (("fp32", TOL32), ("fp64", TOL64)):
+        g = _run(pt, b, "ma", prec)
+        assert np.abs(g - ref).max() <= tol, prec
+    ug = _gim_u(b)
+    refg = O.lc_batch(b, model=1, npol=20, u=ug)
+    g = _run(pt, b, "gimenez", "fp32", npol=20, u=ug)
+    assert np.abs(g - refg).max() <= TOL32
+    bad = [int(b["band_off"][0]) + 5, int(b["band_off"][8]) + 63]   # band 5 of the first, the last of the last
+    b["k"][bad[0]] = -0.1
+    b["u"][bad[1], 0] = np.nan
+    for prec in ("fp32", "fp64"):
+        g = _run(pt, b, "ma", prec)
+        for lc, band in ((0, 5), (8, 63)):
+            o, c = int(b["flux_off"][lc]), int(b["t_count"][lc])
+            blk = g[o:o + (b["band_off"][lc + 1] - b["band_off"][lc]) * c].reshape(-1, c)
+            assert np.all(np.isnan(blk[band])), (prec, lc)
+            rest = np.delete(blk, band, axis=0)
+            r_ref = np.delete(ref[o:o + blk.size].reshape(-1, c), band, axis=0)
+            assert np.abs(rest - r_ref).max() <= (TOL32 if prec == "fp32" else TOL64), (prec, lc)
+            assert np.any(r_ref == 1.0)                 # the light curve has out-of-window exposures
 
 
 def _contact_batch(O, seed, e_max, nss, t_exp):
