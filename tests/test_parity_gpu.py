@@ -178,8 +178,8 @@ def test_batch_spectrophotometric_small(pt, O):
 @pytest.mark.parametrize("npol,nldc", [(1, 1), (5, 3), (60, 4), (61, 2), (100, 4), (512, 2)])
 def test_batch_gimenez_orders_and_laws(pt, O, npol, nldc):
     """The batch's folded Chebyshev rows at small and large npol (rows of more
-    than one wavefront of coefficients, one to many Clenshaw blocks; up to
-    npol = 60 formed in one pass with the band tables, from 61 in two) and
+    than one wavefront of coefficients, one to many Clenshaw blocks, a fold
+    row of exactly 64 coefficients at npol = 60 and one past it at 61) and
     general laws of 1..4 coefficients, FP32 and FP64, against the oracle."""
     from paper_1504_07433_amd import workloads as W
     b = W.config3(n_vec=3, n_band=6, n_exp=300)
