@@ -274,7 +274,7 @@ def alu_roofline(pt, batch, workload, kernel_s):
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32, "traffic": None,
             "peak_nonpacked": PEAK_NONPACKED / 1e12, "frac_nonpacked": achieved / PEAK_NONPACKED,
-            "kernel": "k_lc_batch<fp32, MA> (+ two small setup kernels)", "kernel_ms": kernel_s * 1e3,
+            "kernel": "k_lc_batch<fp32, MA> (+ the window kernel)", "kernel_ms": kernel_s * 1e3,
             "algorithmic_flops_per_launch": flops, **u,
             "hbm_bytes_algorithmic": hbm, "hbm_frac": hbm / kernel_s / HBM_PEAK}
     cnt = COUNTERS.get(workload)

@@ -111,6 +111,7 @@ struct BatchArgs {
   int32_t nldc;
   int32_t npol;
   int32_t model;
+  int32_t nss1;         // every light curve has one subsample: the kernels without supersampled orbits
   // surrogate
   const void* mlp;      // device MlpDev (bf16 weights) or null
   SurEntry* sur_list;   // points left to the network [sur_cap], kSurLists sub-lists
@@ -179,6 +180,8 @@ size_t batch_lds_bytes(int prec, int model);
 hipError_t launch_ma_table(double k_lo, double k_hi, int nk, int nz, float4* tab, hipStream_t s);
 hipError_t prepare_batch_kernels();
 // Workgroups of the batch kernel one compute unit holds at once.
-int batch_blocks_per_cu(int prec, int model);
+// nss1: every light curve of the batch has one subsample (the kernels without
+// the supersampled orbit paths).
+int batch_blocks_per_cu(int prec, int model, bool nss1);
 
 }  // namespace pt

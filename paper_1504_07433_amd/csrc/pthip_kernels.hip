@@ -862,9 +862,17 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
 // The FP64 Mandel-Agol kernel is held to 128 registers: four waves per SIMD
 // instead of three, for about 30 spill slots, nearly all touched once per
 // tile rather than per point.
-template <int PREC, int MODEL, bool LOGL>
+// NSS1: every light curve of the batch has one subsample.  z is then formed
+// at the exposure time and held in a register, and the supersampled orbit
+// paths (LDS chunks, position series, per-band orbits) are not compiled in:
+// fewer registers and scalar spills for the spectrophotometric shape (float
+// Mandel-Agol 125 -> 114 registers, run at five waves per SIMD in 96 with 12
+// spill slots, 0.458 -> 0.442 ms; FP64 Mandel-Agol 28 -> 10 spill slots,
+// 1.248 -> 1.101 ms).
+template <int PREC, int MODEL, bool LOGL, bool NSS1 = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 1, 8))) void k_lc_batch(BatchArgs a) {
+__attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : (NSS1 && PREC == kPrecFP32 && MODEL == kModelMA ? 5 : 1),
+                                   8))) void k_lc_batch(BatchArgs a) {
   using T = typename std::conditional<PREC == kPrecFP64, double, float>::type;
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;
   extern __shared__ unsigned char lds_raw[];
@@ -1037,7 +1045,38 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         }
         continue;
       }
-      if (F32 && MODEL == kModelMA && !SUR && !LOGL && nss <= kZChunk) {
+      if constexpr (NSS1) {
+        static_assert(!SUR && !LOGL && MODEL != kModelMAKhat, "one-subsample kernels write flux");
+        // z at the exposure time, as the general path forms it for one subsample
+        T z1;
+        if constexpr (F32) {
+          const float dm_hi = float(dmid);
+          const float dm_lo = float(dmid - double(dm_hi));
+          const float dm = dm_hi + (dm_lo + fmaf(step_f, 0.0f, base_f));
+          const float z = (dm < of.cut_lo || dm > of.cut_hi) ? far_out : orbit_zf(of, dm);
+          z1 = orbit_ok ? z : NAN;
+        } else {
+          const double ts = tm + texp * (0.5 * inv_nss - 0.5);
+          const T z = orbit_z_from_dm<T, true>(oc, T(mean_anomaly_offset(oc, ts)), far_out);
+          z1 = orbit_ok ? z : T(NAN);
+        }
+        if constexpr (F32 && MODEL == kModelMA) {
+          for (int bnd = bb; bnd < be; ++bnd) {
+            const BandMAView cur = load_uniform(reinterpret_cast<const BandMAView*>(a.bc + bnd));
+            const float acc = ma_loss_view(z1, cur);
+            const float f = cur.w0 == cur.w0 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
+            if (act_lane) flux[fo + (int64_t)(bnd - b0) * cnt + i] = f;
+          }
+        } else {
+          zb[lane] = z1;
+          for (int bnd = bb; bnd < be; ++bnd) {
+            const BandConst bcv = load_uniform(a.bc + bnd);
+            finish(band_loss_sum<PREC, MODEL>(zb, 1, lane, &bcv, bnd, a, gtab + bnd * tab_stride, sur_idx(bnd, i),
+                                              act_lane, n_exact),
+                   bcv, bnd, i, act_lane);
+          }
+        }
+      } else if (F32 && MODEL == kModelMA && !SUR && !LOGL && nss <= kZChunk) {
         // the float Mandel-Agol path: one orbit solve per (exposure,
         // subsample), then per band only the leading 32 bytes of its
         // constants (one scalar load instead of three: 0.564 -> 0.545 ms on
@@ -1136,8 +1175,22 @@ hipError_t prepare_batch_kernels() {
   return hipSuccess;
 }
 
+// The one-subsample kernels exist for these (precision, model) pairs.
+static bool has_nss1(int prec, int model) {
+  if (prec == kPrecFP64) return model == kModelMA || model == kModelGimenez;
+  return prec == kPrecFP32 && (model == kModelMA || model == kModelMAInterp || model == kModelGimenez);
+}
+
 // The flux-writing batch kernel for (prec, model), for occupancy queries.
-static const void* batch_kernel(int prec, int model) {
+static const void* batch_kernel(int prec, int model, bool nss1) {
+  if (nss1 && has_nss1(prec, model)) {
+    if (prec == kPrecFP64)
+      return model == kModelMA ? (const void*)k_lc_batch<kPrecFP64, kModelMA, false, true>
+                               : (const void*)k_lc_batch<kPrecFP64, kModelGimenez, false, true>;
+    if (model == kModelMA) return (const void*)k_lc_batch<kPrecFP32, kModelMA, false, true>;
+    if (model == kModelMAInterp) return (const void*)k_lc_batch<kPrecFP32, kModelMAInterp, false, true>;
+    return (const void*)k_lc_batch<kPrecFP32, kModelGimenez, false, true>;
+  }
   if (prec == kPrecFP64)
     return model == kModelMA ? (const void*)k_lc_batch<kPrecFP64, kModelMA, false>
                              : (const void*)k_lc_batch<kPrecFP64, kModelGimenez, false>;
@@ -1152,9 +1205,9 @@ static const void* batch_kernel(int prec, int model) {
   }
 }
 
-int batch_blocks_per_cu(int prec, int model) {
+int batch_blocks_per_cu(int prec, int model, bool nss1) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(prec, model), kBlock,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(prec, model, nss1), kBlock,
                                                    batch_lds_bytes(prec, model)) != hipSuccess)
     return 2;
   return nb < 1 ? 1 : nb;
@@ -1163,6 +1216,19 @@ int batch_blocks_per_cu(int prec, int model) {
 template <bool LOGL>
 static void launch_main(const BatchArgs& a, int prec, int model, dim3 grid, size_t lds, hipStream_t s) {
   const dim3 block(kBlock);
+  if (!LOGL && a.nss1 && has_nss1(prec, model)) {
+    if (prec == kPrecFP64) {
+      if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelMA, false, true>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelGimenez, false, true>), grid, block, lds, s, a);
+    } else if (model == kModelMA) {
+      hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMA, false, true>), grid, block, lds, s, a);
+    } else if (model == kModelMAInterp) {
+      hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelMAInterp, false, true>), grid, block, lds, s, a);
+    } else {
+      hipLaunchKernelGGL((k_lc_batch<kPrecFP32, kModelGimenez, false, true>), grid, block, lds, s, a);
+    }
+    return;
+  }
   if (prec == kPrecFP64) {
     if (model == kModelMA) hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelMA, LOGL>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((k_lc_batch<kPrecFP64, kModelGimenez, LOGL>), grid, block, lds, s, a);

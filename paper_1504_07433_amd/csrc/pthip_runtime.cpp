@@ -199,6 +199,7 @@ struct Plan {
   DevBuf d_t_start, d_t_count, d_nss, d_band_off, d_flux_off, d_n_obs, oc, ocf, bc, gtab, gtab64, queue, khat, ztab,
       ltab, sur;
   int64_t sur_cap = 0;   // surrogate: list entries (sur holds the sub-list counters, then the list)
+  bool all_nss1 = false;  // every light curve has one subsample
   std::map<std::pair<int, int64_t>, std::unique_ptr<TileSet>> tilesets;  // by tile size and split tail
   LaunchShape shape;
   bool tuned = false;
@@ -398,7 +399,7 @@ static std::string stream_key(const std::string& shape_key, hipStream_t s) {
 static pt_status default_shape(const pt_batch* b, const Plan* p, LaunchShape* out) {
   out->tile_e = default_tile(b);
   if (prepare_batch_kernels() != hipSuccess) return fail(PT_ERR_HIP, "kernel attributes");
-  const int resident = batch_blocks_per_cu(kernel_prec(p), p->model);
+  const int resident = batch_blocks_per_cu(kernel_prec(p), p->model, p->all_nss1);
   out->workgroups = std::max(1, cu_count()) * std::max(1, resident * 3 / 2);
   return PT_OK;
 }
@@ -425,6 +426,7 @@ static pt_status get_plan(const pt_batch* b, pt_model model, int32_t npol, pt_pr
   const size_t n = (size_t)b->n_lc;
   p->t_count.assign(b->t_count, b->t_count + n);
   p->nss.assign(b->nss, b->nss + n);
+  p->all_nss1 = std::all_of(p->nss.begin(), p->nss.end(), [](int32_t v) { return v == 1; });
   p->band_off.assign(b->band_off, b->band_off + n + 1);
   PT_HIP(p->d_t_start.ensure(std::max<size_t>(1, n) * 8));
   PT_HIP(p->d_t_count.ensure(std::max<size_t>(1, n) * 8));
@@ -490,6 +492,7 @@ static pt_status fill_args(const pt_batch* b, Plan* p, const LaunchShape& shape,
   a->t_start = (const int64_t*)p->d_t_start.p;
   a->t_count = (const int64_t*)p->d_t_count.p;
   a->nss = (const int32_t*)p->d_nss.p;
+  a->nss1 = p->all_nss1 ? 1 : 0;
   a->band_off = (const int32_t*)p->d_band_off.p;
   a->flux_off = (const int64_t*)p->d_flux_off.p;
   a->tiles = (const TileDesc*)ts->tiles.p;
@@ -1090,6 +1093,7 @@ pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec pre
   // launch shape: a tuned one for this batch shape if there is one, else the
   // default; tiles grow until the tile list fits the staging area
   int tile_e = 0, wg = 0;
+  const bool nss1 = std::all_of(batch->nss, batch->nss + n_lc, [](int32_t v) { return v == 1; });
   auto tu = g_tuned.find(tune_key(plan_key(batch, model, 0, prec)));
   if (tu != g_tuned.end()) {
     const LaunchShape ts = tuned_for_device(tu->second);
@@ -1098,7 +1102,7 @@ pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec pre
   } else {
     tile_e = default_tile(batch);
     const int kp = prec == PT_PREC_FP64 ? kPrecFP64 : kPrecFP32;
-    wg = std::max(1, cu_count()) * std::max(1, batch_blocks_per_cu(kp, kModelMA) * 3 / 2);
+    wg = std::max(1, cu_count()) * std::max(1, batch_blocks_per_cu(kp, kModelMA, nss1) * 3 / 2);
   }
   int64_t n_tiles = count_tiles(batch, tile_e);
   NoAllocLayout L = noalloc_layout(n_lc, n_band, n_tiles);
@@ -1131,6 +1135,7 @@ pt_status pt_lc_batch_noalloc(const pt_batch* batch, pt_model model, pt_prec pre
   a.t_start = (const int64_t*)(D.ptr + L.t_start);
   a.t_count = (const int64_t*)(D.ptr + L.t_count);
   a.nss = (const int32_t*)(D.ptr + L.nss);
+  a.nss1 = nss1 ? 1 : 0;
   a.band_off = (const int32_t*)(D.ptr + L.band_off);
   a.flux_off = (const int64_t*)(D.ptr + L.flux_off);
   a.tiles = (const TileDesc*)(D.ptr + L.tiles);
