@@ -482,12 +482,16 @@ def test_full_spectrophotometric_sampled(pt, O):
     b = W.config3()
     _sampled_check(pt, O, b, "ma", "fp32", TOL32, 400)
     _sampled_check(pt, O, b, "gimenez", "fp32", TOL32, 150, u=_gim_u(b), seed=2)
+    # the FP64 kernels of the one-subsample shape
+    _sampled_check(pt, O, b, "ma", "fp64", TOL64, 300, seed=3)
+    _sampled_check(pt, O, b, "gimenez", "fp64", 1e-12, 100, u=_gim_u(b), seed=4)
 
 
 def test_full_uneven_sampled(pt, O):
     from paper_1504_07433_amd import workloads as W
     b = W.config4()
     _sampled_check(pt, O, b, "ma", "fp32", TOL32, 1500)
+    _sampled_check(pt, O, b, "ma", "fp64", TOL64, 500, seed=1)
 
 
 # --- fused likelihood -------------------------------------------------------------------
