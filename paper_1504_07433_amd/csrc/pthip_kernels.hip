@@ -484,17 +484,20 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
     // Per-exposure position series for the float path: for each order the
     // smallest truncation bound over 64 circles inside the analytic strip
     // (one per lane); the light curve takes the lowest order that holds.
+    // (light curves with fewer subsamples solve per subsample: no bound needed)
     const int nss = a.nss[lc];
-    const double dmax = 2.0 * kPi * o.inv_p * a.t_exp[lc] * (0.5 - 0.5 / nss) + 1e-6;
-    const double tcap = o.e > 0.0 && o.e < 1.0 ? acosh(1.0 / o.e) : 8.0;
-    double rem[kOrbitSeriesMax - kOrbitSeriesMin + 1];
-    orbit_series_bounds(o, dmax, tcap * (lane + 1) / (kWave + 1), rem);
     int order = 0;
+    if (nss >= kOrbitSeriesMinSubsamples) {
+      const double dmax = 2.0 * kPi * o.inv_p * a.t_exp[lc] * (0.5 - 0.5 / nss) + 1e-6;
+      const double tcap = o.e > 0.0 && o.e < 1.0 ? acosh(1.0 / o.e) : 8.0;
+      double rem[kOrbitSeriesMax - kOrbitSeriesMin + 1];
+      orbit_series_bounds(o, dmax, tcap * (lane + 1) / (kWave + 1), rem);
 #pragma unroll
-    for (int n = kOrbitSeriesMax; n >= kOrbitSeriesMin; --n) {
-      double r = rem[n - kOrbitSeriesMin];
-      for (int off = 32; off > 0; off >>= 1) r = fmin(r, __shfl_xor(r, off));
-      if (r <= kOrbitSeriesTol) order = n;
+      for (int n = kOrbitSeriesMax; n >= kOrbitSeriesMin; --n) {
+        double r = rem[n - kOrbitSeriesMin];
+        for (int off = 32; off > 0; off >>= 1) r = fmin(r, __shfl_xor(r, off));
+        if (r <= kOrbitSeriesTol) order = n;
+      }
     }
     if (lane == 0) {
       a.oc[lc] = o;
