@@ -298,6 +298,34 @@ def test_band_split_tiles_match_oracle(pt, O):
             assert np.any(r_ref == 1.0)                 # the light curve has out-of-window exposures
 
 
+def test_batch_extreme_shapes(pt, O):
+    """A light curve with 40,000 bands (more than a tile may be split over:
+    its tiles stay whole), one with 200 subsamples (13 LDS chunks, the orbit
+    per band), and one of a single exposure and band, against the oracle."""
+    from paper_1504_07433_amd import workloads as W
+    rng = np.random.default_rng(21)
+    nb = np.array([40000, 3, 1], np.int64)
+    cnt = np.array([7, 50, 1], np.int64)
+    b = W._empty_batch(3)
+    b["t0"][:] = [0.0, 0.005, -0.003]
+    b["P"][:] = 3.0
+    b["aR"][:] = [10.0, 8.0, 12.0]
+    b["b"][:] = [0.3, 0.5, 0.1]
+    b["e"][:] = [0.0, 0.2, 0.1]
+    b["w"][:] = [0.0, 1.0, 4.0]
+    b["t_exp"][:] = [0.001, 0.02, 0.01]
+    b["nss"][:] = [1, 200, 1]
+    t = np.concatenate([np.linspace(-0.06, 0.06, 7), np.linspace(-0.08, 0.08, 50), [0.0]])
+    k = rng.uniform(0.05, 0.15, int(nb.sum()))
+    u = np.stack([rng.uniform(0.1, 0.6, len(k)), rng.uniform(0.0, 0.3, len(k))], 1)
+    b = W._finish(b, t, [0, 7, 57], cnt, nb, k, u, "extreme")
+    ref = O.lc_batch(b, model=0)
+    assert np.count_nonzero(ref < 1.0) > len(ref) // 4
+    for prec, tol in (("fp32", TOL32), ("fp64", TOL64)):
+        g = _run(pt, b, "ma", prec)
+        assert np.abs(g - ref).max() <= tol, prec
+
+
 def _contact_batch(O, seed, e_max, nss, t_exp):
     """Light curves sampled densely around their first and last contacts
     (located on the oracle's z), eccentric orbits up to e_max, two bands per
@@ -454,10 +482,22 @@ def test_autotune_keeps_results(pt, tmp_path):
 
 # --- full sizes, in the benchmark's launch configuration, on sampled outputs ----
 
+def _bench_shapes(pt):
+    """The tuned launch shapes bench.py loads, so that the full-size checks
+    run the launch configuration the benchmark times."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1504_07433_amd", "data", "tune_cache.jsonl")
+    assert pt.tune_load(path) >= 1
+
+
 def _sampled_check(pt, O, b, model, prec, tol, n_samples, npol=50, u=None, seed=0):
+    _bench_shapes(pt)
     db = pt.DeviceBatch(b, u=u)
     import torch
     g = pt.lc_batch(db, model, npol=npol, prec=prec)
+    say(b["name"], model, prec, "launch shape (tile exposures, workgroups)",
+        pt.launch_shape(db, model, npol=npol, prec=prec))
     pairs = random_pairs(b, n_samples, seed=seed)
     sb, idx = single_exposure_subset(b, pairs)
     if u is not None:
