@@ -284,11 +284,13 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
 // m = 1 - kc^2 and c_(j+1) = (a_j - g_j) / 2 = (mu_j - kk_j) / 2^(j+1); so only
 // the third-kind integral carries its own (p, a, b) through the steps, and
 // no step needs the product of two p.  The arguments are ckce = c_K + c_E,
-// ce8 = -c_E / 8, sqrt(p) and b / sqrt(p).  On exit after steps 0..J, mu is
-// 2^(J+1) times the next arithmetic mean, whose relative distance from M
-// is about (a_J - g_J)^2 / (16 a_J^2): the same convergence test as cel.
+// ce8 = -c_E / 8, sqrt(p) and b / sqrt(p); the result is scaled by
+// 1 / sqrt(pq), taken with the final reciprocal as one reciprocal square
+// root.  On exit after steps 0..J, mu is 2^(J+1) times the next arithmetic
+// mean, whose relative distance from M is about (a_J - g_J)^2 / (16 a_J^2):
+// the same convergence test as cel.
 template <class Op>
-PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a, double bt) {
+PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a, double bt, double pq) {
   double mu = 1.0, kk = kc, prod = kc;
   double p = sp, b = bt;
   double s8 = 4.0 * fma(-kc, kc, 1.0);   // 8 sum 2^(n-1) c_n^2, so far n = 0
@@ -315,10 +317,12 @@ PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a,
   for (; it < 40; ++it)
     if (!step(true)) break;
   // w = 2^-J now: K = pi 2^J / mu = pi / (mu w), and the third-kind integral
-  // is (pi/2) (b + a mu) / (mu (mu + p)); one reciprocal for both
+  // is (pi/2) (b + a mu) / (mu (mu + p)); one reciprocal for both and the
+  // prefactor, 1 / (sqrt(pq) X) = 1 / sqrt(pq X^2) with X = mu (mu + p) w > 0
   const double mp = mu + p;
   const double x = fma(ce8, s8, ckce);   // c_K + c_E (1 - sum)
-  const double rd = kPi * Op::rcp(mu * mp * w);
+  const double X = mu * mp * w;
+  const double rd = kPi * Op::rsqrt(pq * X * X);
   return fma(x, mp, 0.5 * w * fma(a, mu, b)) * rd;
 }
 
@@ -688,11 +692,12 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 // Shared elliptic part.  In the limb region (1-k < z < 1+k; the paper's case
 // with lambda_1) and inside the disc (z < 1-k, k < 1/2; lambda_2) the
 // elliptic combination is
-//   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)]
+//   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)],  pref = 1 / sqrt(pq),
 // with kc = sqrt(1 - m) formed without cancellation.  C_P Pi is one cel with
 // p = 1 - n; C_K K + C_E E is a second cel with p = 1, or, in double, comes
-// from the mean that the first one runs (ma_elliptic).
-template <class T> struct MaEllTerms { T kc, ck, ce, sp, cp, bt2, pref; };
+// from the mean that the first one runs (ma_elliptic), whose last
+// reciprocal then takes the prefactor's square root with it.
+template <class T> struct MaEllTerms { T kc, ck, ce, sp, cp, bt2, pq; };
 
 template <class T, class Op>
 PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
@@ -701,7 +706,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
   const T azmk = fabs(zmk);
   const T sgn = zmk > T(0) ? T(1) : T(-1);
   const T rz = Op::rcp(azmk);                              // 1 / |z-k| = sqrt(1/a)
-  T kc, ck, ce, sp, pref, bt2;
+  T kc, ck, ce, sp, pq, bt2;
   if (limb) {
     const T a = zmk * zmk, b = zpk * zpk;
     const T q = (k - z) * (k + z);
@@ -710,7 +715,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
     ck = (T(1) - b) * (T(2) * b + a - T(3)) - T(3) * q * (b - T(2));
     ce = T(4) * z * k * (z2 + T(7) * k2 - T(4));
     sp = rz;                                              // sqrt(p) = sqrt(1/a)
-    pref = T(1.0 / (9.0 * kPi)) * Op::rsqrt(k * z);
+    pq = T(81.0 * kPi * kPi) * (k * z);                   // pref = 1 / (9 pi sqrt(k z))
     bt2 = T(3) * zpk * sgn;                               // C_P / sqrt(p)
   } else {
     const T q = (k - z) * (k + z);
@@ -720,12 +725,12 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
     ck = T(1) - T(5) * z2 + k2 + q * q;
     ce = oma * (z2 + T(7) * k2 - T(4));
     sp = zpk * rz;                                        // sqrt(p) = sqrt(b/a)
-    pref = T(2.0 / (9.0 * kPi)) * Op::rsqrt(oma);
+    pq = T(81.0 * kPi * kPi / 4.0) * oma;                 // pref = 2 / (9 pi sqrt(1 - a))
     bt2 = T(3) * sgn;                                     // C_P / sqrt(p)
   }
   // C_P = -3 q / a = 3 (z+k) / (z-k) = 3 sign(z-k) (z+k) / |z-k|
   const T cp = T(3) * sgn * zpk * rz;
-  return MaEllTerms<T>{kc, ck, ce, sp, cp, bt2, pref};
+  return MaEllTerms<T>{kc, ck, ce, sp, cp, bt2, pq};
 }
 
 // In double, K and E come from the mean that drives the third-kind integral
@@ -734,10 +739,10 @@ template <class T, int ITERS, class Op = Num<T>>
 PT_HD T ma_elliptic(T z, T k, bool limb) {
   const MaEllTerms<T> e = ma_elliptic_terms<T, Op>(z, k, limb);
   if constexpr (std::is_same<T, double>::value && ITERS == 0) {
-    return e.pref * cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.cp, e.bt2);
+    return cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.cp, e.bt2, e.pq);
   } else {
     const CelPair<T> r = cel2<T, ITERS, Op>(e.kc, T(1), e.ck + e.ce, e.ck + e.ce * e.kc * e.kc, e.sp, e.cp, e.bt2);
-    return e.pref * (r.r1 + r.r2);
+    return Op::rsqrt(e.pq) * (r.r1 + r.r2);
   }
 }
 
