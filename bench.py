@@ -44,8 +44,8 @@ SURROGATE_CKPT = os.path.join(ROOT, "paper_1504_07433_amd", "data", "surrogate.n
 # profiles/unit_probes_flops.txt):
 F_ORBIT_ECC = 86.0        # orbit of one in-transit point, e > 0: Kepler, z (float part)
 F_ORBIT_CIRC = 40.0       # the same for e = 0
-F_MA_INSIDE = 195.5       # Mandel-Agol functions + limb darkening, z < 1 - k
-F_MA_LIMB = 287.3         # the same, 1 - k < z < 1 + k
+F_MA_INSIDE = 191.5       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 283.3         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8);
 # each further band of a point out of transit its accumulation and flux (2).
@@ -58,8 +58,8 @@ F_POINT, F_EXPOSURE, F_BAND_OUT = 5.0, 8.0, 2.0
 # in-transit point (phase, one Kepler solve, series coefficients, flux).  The
 # probes run at series order 4; order-5 light curves spend ~4 flops more per
 # point and ~20 more per exposure, which the model does not charge.
-F_SER_INSIDE = 156.9
-F_SER_LIMB = 242.9
+F_SER_INSIDE = 152.9
+F_SER_LIMB = 238.9
 F_SER_EXPOSURE = 228.3
 SERIES_NSS = (4, 16)
 # MI355X published peaks.  The FP32 vector peak counts packed FP32 FMAs (two
@@ -84,7 +84,7 @@ NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 # counters read for an elementwise kernel that reads and writes 1 GiB
 # (FETCH_SIZE 524309.7 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB written).
 COUNTERS = {
-    "spectrophotometric": {"valu_insts": 1.77299e8, "fetch_kib": 61059.6, "write_kib": 468100.0},
+    "spectrophotometric": {"valu_insts": 1.76871e8, "fetch_kib": 71773.6, "write_kib": 464609.0},
     "long-cadence": {"valu_insts": 8.13972e8, "fetch_kib": 10816.8, "write_kib": 204911.0},
     "uneven": {"valu_insts": 6.94268e9, "fetch_kib": 381527.0, "write_kib": 2845240.0},
 }
