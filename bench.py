@@ -85,8 +85,8 @@ NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 # (FETCH_SIZE 524309.7 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB written).
 COUNTERS = {
     "spectrophotometric": {"valu_insts": 1.76871e8, "fetch_kib": 71773.6, "write_kib": 464609.0},
-    "long-cadence": {"valu_insts": 8.13972e8, "fetch_kib": 10816.8, "write_kib": 204911.0},
-    "uneven": {"valu_insts": 6.94268e9, "fetch_kib": 381527.0, "write_kib": 2845240.0},
+    "long-cadence": {"valu_insts": 8.06182e8, "fetch_kib": 10626.4, "write_kib": 204399.0},
+    "uneven": {"valu_insts": 6.86191e9, "fetch_kib": 381192.0, "write_kib": 2845500.0},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524309.7, 1.0
 
