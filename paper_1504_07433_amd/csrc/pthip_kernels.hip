@@ -452,7 +452,20 @@ __global__ __launch_bounds__(256) void k_lc_window(BatchArgs a) {
     }
     OrbitConst o = orbit_const(a.t0[lc], a.P[lc], a.aR[lc], a.b[lc], a.e[lc], a.w[lc], kmax);
     o.bands_ok = __all(ok) ? 1 : 0;
-    if (o.valid && o.dm_cut < kPi) {
+    const double ci2 = o.cos_i * o.cos_i;
+    if (o.valid && o.circular && ci2 < 1.0 - 1e-9) {
+      // circular orbit: on the near side z^2 = (a/R*)^2 (cos^2 i + sin^2 i
+      // sin^2 dM), so z < 1 + k_max exactly where sin^2 dM < S
+      const double S = ((1.0 + kmax) * (1.0 + kmax) / (o.aR * o.aR) - ci2) / (1.0 - ci2);
+      if (!(S > 0.0)) {
+        o.cut_lo = 1.0;                         // empty window: never in transit
+        o.cut_hi = -1.0;
+      } else {
+        const double h = asin(fmin(1.0, sqrt(S))) * (1.0 + 1e-9) + 1e-12;
+        o.cut_lo = -h;
+        o.cut_hi = h;
+      }
+    } else if (o.valid && o.dm_cut < kPi) {
       const double C = o.dm_cut;
       const double L = o.aR * sqrt((1.0 + o.e) / (1.0 - o.e)) * (1.0 + 1e-9);
       const double thr = 1.0 + kmax;

@@ -363,6 +363,19 @@ def _contact_batch(O, seed, e_max, nss, t_exp):
 
 
 @pytest.mark.parametrize("nss,t_exp", [(1, 0.0), (7, 0.0204)])
+def test_batch_circular_contacts(pt, O, nss, t_exp):
+    """Circular orbits (their in-transit window in closed form), impact
+    parameters up to 1.15, times dense around every contact."""
+    b = _contact_batch(O, 31 + nss, 0.0, nss, t_exp)
+    assert np.all(b["e"] == 0.0)
+    ref = O.lc_batch(b, model=0)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        got = _run(pt, b, "ma", prec)
+        say("circular contacts", prec, "max|dF|", np.abs(got - ref).max())
+        assert np.abs(got - ref).max() <= tol, prec
+
+
+@pytest.mark.parametrize("nss,t_exp", [(1, 0.0), (7, 0.0204)])
 def test_batch_eccentric_contacts(pt, O, nss, t_exp):
     b = _contact_batch(O, 11 + nss, 0.85, nss, t_exp)
     ref = O.lc_batch(b, model=0)
