@@ -877,7 +877,9 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
 // partial sum per tile (summed per light curve by k_loglike_reduce).
 // The FP64 Mandel-Agol kernel is held to 128 registers: four waves per SIMD
 // instead of three, for about 30 spill slots, nearly all touched once per
-// tile rather than per point.
+// tile rather than per point.  The float Mandel-Agol flux kernel is held to
+// the same four waves (it needs 128 or 129 registers, depending on how the
+// compiler schedules the limb angles: two spill slots at most).
 // NSS1: every light curve of the batch has one subsample.  z is then formed
 // at the exposure time and held in a register, and the supersampled orbit
 // paths (LDS chunks, position series, per-band orbits) are not compiled in:
@@ -887,7 +889,7 @@ __device__ __forceinline__ T band_loss_sum(const T* zb, int ns, int lane, const 
 // 1.248 -> 1.101 ms).
 template <int PREC, int MODEL, bool LOGL, bool NSS1 = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : (NSS1 && PREC == kPrecFP32 && MODEL == kModelMA ? 5 : 1),
+__attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : (PREC == kPrecFP32 && MODEL == kModelMA && !LOGL ? (NSS1 ? 5 : 4) : 1),
                                    8))) void k_lc_batch(BatchArgs a) {
   using T = typename std::conditional<PREC == kPrecFP64, double, float>::type;
   constexpr bool SUR = PREC == kPrecSurrogate || PREC == kPrecSurrogateBf16;

@@ -86,6 +86,21 @@ template <> struct Num<float> {
     r = y > ax ? 1.57079632679489662f - r : r;
     return x < 0.0f ? 3.14159265358979324f - r : r;
   }
+  // atan2 for 0 <= y <= x / sqrt(3) (an angle of at most 30 degrees): atan of
+  // t = y / x by an odd polynomial of degree 11 fitted to atan on
+  // [0, 0.578] by Lawson's iteratively reweighted least squares (maximum
+  // error 5.7e-9).
+  PT_HD static float atan2_narrow(float y, float x) {
+    const float t = y * rcp(x);
+    const float t2 = t * t;
+    float p = -4.0179652225e-02f;
+    p = p * t2 + 9.3659724248e-02f;
+    p = p * t2 - 1.3969967240e-01f;
+    p = p * t2 + 1.9971194144e-01f;
+    p = p * t2 - 3.3332188301e-01f;
+    p = p * t2 + 9.9999986908e-01f;
+    return t * p;
+  }
   PT_HD static void sincos(float x, float* s, float* c) {
 #if defined(__HIP_DEVICE_COMPILE__)
     ::sincosf(x, s, c);
@@ -106,6 +121,7 @@ template <> struct Num<double> {
   PT_HD static double sqrt2(double x) { return 2.0 * ::sqrt(x); }
   PT_HD static double rsqrt(double x) { return 1.0 / ::sqrt(x); }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
+  PT_HD static double atan2_narrow(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) {
 #if defined(__HIP_DEVICE_COMPILE__)
     ::sincos(x, s, c);
@@ -172,11 +188,14 @@ struct NumFast {
   }
   PT_HD static double atan2(double y, double x) { return ::atan2(y, x); }
   PT_HD static void sincos(double x, double* s, double* c) { Num<double>::sincos(x, s, c); }
-  // The mean's relative spread falls quadratically, so stopping at 3e-4 leaves
-  // <= 3.7e-9 in the elliptic combination (measured over k <= 1/2 and all z),
-  // below what the float rounding of z moves the flux; 3e-5 (3.6e-11) costs
-  // 0.3 more Gauss steps per point.
-  static constexpr double cel_tol = 3e-4;
+  // The mean's relative spread falls quadratically, and the error that
+  // stopping leaves in the elliptic combination grows as the square of the
+  // tolerance: about 8e-3 tol^2 at most over k <= 1/2 and all z (measured
+  // against Carlson's integrals: 3.3e-6 at 2e-2, 8.9e-7 at 1e-2).  At 2e-3
+  // that is 3.3e-8, below the ~1e-7 of the unrefined seeds, and saves a
+  // fourth Gauss step for about 7 % of the points of a transit (3e-4 left
+  // 3.7e-9).
+  static constexpr double cel_tol = 2e-3;
   // The first two Gauss steps run without the convergence test: a wave of
   // the float path nearly always needs them, and the test with its branch
   // costs about a fifth of a step (a third unchecked step costs more than the
@@ -285,8 +304,8 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
 // the third-kind integral carries its own (p, a, b) through the steps, and
 // no step needs the product of two p.  The arguments are ckce = c_K + c_E,
 // ce8 = -c_E / 8, sqrt(p) and b / sqrt(p); the result is scaled by
-// 1 / sqrt(pq), taken with the final reciprocal as one reciprocal square
-// root.  On exit after steps 0..J, mu is 2^(J+1) times the next arithmetic
+// 1 / (9 pi sqrt(pq)), taken with the final reciprocal as one reciprocal
+// square root.  On exit after steps 0..J, mu is 2^(J+1) times the next arithmetic
 // mean, whose relative distance from M is about (a_J - g_J)^2 / (16 a_J^2):
 // the same convergence test as cel.
 template <class Op>
@@ -318,11 +337,12 @@ PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a,
     if (!step(true)) break;
   // w = 2^-J now: K = pi 2^J / mu = pi / (mu w), and the third-kind integral
   // is (pi/2) (b + a mu) / (mu (mu + p)); one reciprocal for both and the
-  // prefactor, 1 / (sqrt(pq) X) = 1 / sqrt(pq X^2) with X = mu (mu + p) w > 0
+  // prefactor, pi / (9 pi sqrt(pq) X) = (1/9) / sqrt(pq X^2) with
+  // X = mu (mu + p) w > 0
   const double mp = mu + p;
   const double x = fma(ce8, s8, ckce);   // c_K + c_E (1 - sum)
   const double X = mu * mp * w;
-  const double rd = kPi * Op::rsqrt(pq * X * X);
+  const double rd = (1.0 / 9.0) * Op::rsqrt(pq * X * X);
   return fma(x, mp, 0.5 * w * fma(a, mu, b)) * rd;
 }
 
@@ -692,7 +712,7 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 // Shared elliptic part.  In the limb region (1-k < z < 1+k; the paper's case
 // with lambda_1) and inside the disc (z < 1-k, k < 1/2; lambda_2) the
 // elliptic combination is
-//   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)],  pref = 1 / sqrt(pq),
+//   pref * [C_K K(m) + C_E E(m) + C_P Pi(n, m)],  pref = 1 / (9 pi sqrt(pq)),
 // with kc = sqrt(1 - m) formed without cancellation.  C_P Pi is one cel with
 // p = 1 - n; C_K K + C_E E is a second cel with p = 1, or, in double, comes
 // from the mean that the first one runs (ma_elliptic), whose last
@@ -715,7 +735,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
     ck = (T(1) - b) * (T(2) * b + a - T(3)) - T(3) * q * (b - T(2));
     ce = T(4) * z * k * (z2 + T(7) * k2 - T(4));
     sp = rz;                                              // sqrt(p) = sqrt(1/a)
-    pq = T(81.0 * kPi * kPi) * (k * z);                   // pref = 1 / (9 pi sqrt(k z))
+    pq = k * z;                                           // pref = 1 / (9 pi sqrt(k z))
     bt2 = T(3) * zpk * sgn;                               // C_P / sqrt(p)
   } else {
     const T q = (k - z) * (k + z);
@@ -725,7 +745,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
     ck = T(1) - T(5) * z2 + k2 + q * q;
     ce = oma * (z2 + T(7) * k2 - T(4));
     sp = zpk * rz;                                        // sqrt(p) = sqrt(b/a)
-    pq = T(81.0 * kPi * kPi / 4.0) * oma;                 // pref = 2 / (9 pi sqrt(1 - a))
+    pq = T(0.25) * oma;                                   // pref = 2 / (9 pi sqrt(1 - a))
     bt2 = T(3) * sgn;                                     // C_P / sqrt(p)
   }
   // C_P = -3 q / a = 3 (z+k) / (z-k) = 3 sign(z-k) (z+k) / |z-k|
@@ -742,14 +762,16 @@ PT_HD T ma_elliptic(T z, T k, bool limb) {
     return cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.cp, e.bt2, e.pq);
   } else {
     const CelPair<T> r = cel2<T, ITERS, Op>(e.kc, T(1), e.ck + e.ce, e.ck + e.ce * e.kc * e.kc, e.sp, e.cp, e.bt2);
-    return Op::rsqrt(e.pq) * (r.r1 + r.r2);
+    return T(1.0 / (9.0 * kPi)) * Op::rsqrt(e.pq) * (r.r1 + r.r2);
   }
 }
 
 // lambda_e and eta_1 in the limb region, with the square root of
 // D = 4z^2 - (1+z^2-k^2)^2 = (z-(1-k))(1+k-z)(1+z-k)(1+z+k) formed as a
 // product and the two angles by atan2 (no acos near +-1); sqrt(D) >= 0, so
-// both angles lie in [0, pi].
+// both angles lie in [0, pi].  The angle at the star's centre, kappa_1, has
+// tan kappa_1 = sqrt(D) / (1 - k^2 + z^2) <= 1/sqrt(3) for k <= 1/2 (at most
+// 30 degrees, reached at k = 1/2), the only radius ratios that come here.
 template <class T>
 PT_HD void ma_limb_terms(T z, T k, T* le, T* ed) {
   const T k2 = k * k, z2 = z * z;
@@ -757,7 +779,7 @@ PT_HD void ma_limb_terms(T z, T k, T* le, T* ed) {
   D = D > T(0) ? D : T(0);
   const T sD = Num<T>::sqrt(D);
   const T kap0 = Num<T>::atan2(sD, k2 + z2 - T(1));
-  const T kap1 = Num<T>::atan2(sD, T(1) - k2 + z2);
+  const T kap1 = Num<T>::atan2_narrow(sD, T(1) - k2 + z2);
   *le = (k2 * kap0 + kap1 - T(0.5) * sD) * T(1.0 / kPi);
   const T eta2 = T(0.5) * k2 * (k2 + T(2) * z2);
   *ed = (kap1 + T(2) * eta2 * kap0 - T(0.25) * (T(1) + T(5) * k2 + z2) * sD) * T(0.5 / kPi);
