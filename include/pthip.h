@@ -249,11 +249,11 @@ pt_status pt_batch_launch_shape(const pt_batch* batch, pt_model model, int32_t n
  *   model   PT_MODEL_MA_QUAD only (else PT_ERR_UNSUPPORTED)
  *   prec    PT_PREC_FP32 or PT_PREC_FP64 (else PT_ERR_UNSUPPORTED)
  *   batch, flux as for pt_lc_batch
- * Limits: about 272 bytes per light curve, 104 per passband and 16 per tile
+ * Limits: about 272 bytes per light curve, 136 per passband and 16 per tile
  * (each part rounded up to 256 bytes, plus 1 KiB of counters) must fit the
  * 16 MiB, and the shape arrays with the tile list the 8 MiB staging area;
  * tiles are made longer until the tile list fits, and a batch that does not
- * fit even then (e.g. more than about 160,000 passbands) gives PT_ERR_ARG
+ * fit even then (e.g. more than about 120,000 passbands) gives PT_ERR_ARG
  * with the sizes, before any HIP call.
  * Every call on one GPU shares that GPU's array: calls on one GPU whose
  * executions overlap (different streams, or threads) race and give wrong

@@ -15,25 +15,31 @@ namespace pt {
 // positive and its weights finite, and an invalid band has NaN weights.
 struct BandConst {
   double kd;            // radius ratio
+  double c7d;           // 7 k^2 - 4 (the radius ratio's part of C_E)
   float kf;             // radius ratio, float
-  float wf[3];          // loss weights in float (MA: (1-c)/N, c/N, u2/N)
+  float k2f;            // k^2, float
+  float w1;             // weight of lambda_d in float (= wf[1])
   float onepk;          // 1 + k (float), out-of-transit test
   float omk;            // 1 - k (float)
-  double wd[5];         // loss weights in double (MA: the three above; Gimenez: C_0..C_N)
+  float ma_in[2];       // float Mandel-Agol loss inside the disc (ma_loss_coefficients)
+  float ma_limb[5];     // the same on the limb
+  float wf[3];          // loss weights in float (MA: (1-c)/N, c/N, u2/N)
   float inv1pk;         // 1 / (1 + k) (float), Gimenez c = z/(1+k)
+  double wd[5];         // loss weights in double (MA: the three above; Gimenez: C_0..C_N)
   int32_t exact;        // k > 1/2: Mandel-Agol through the exact double path
-  double inv1pkd;       // 1 / (1 + k) (double)
   int32_t valid;        // k > 0 and finite weights
-  int32_t pad;
+  double inv1pkd;       // 1 / (1 + k) (double)
 };
 
-// The leading part of BandConst the float Mandel-Agol band loop reads:
-// exact is kd > 1/2, valid is w0 not NaN.
+// The leading 64 bytes of BandConst, what the float Mandel-Agol band loop
+// reads per band (one scalar load): exact is kd > 1/2, valid is w1 not NaN.
 struct BandMAView {
-  double kd;
-  float kf, w0, w1, w2, onepk, omk;
+  double kd, c7d;
+  float kf, k2f, w1, onepk, omk;
+  float ma_in[2], ma_limb[5];
 };
-static_assert(offsetof(BandConst, omk) + sizeof(float) == sizeof(BandMAView), "BandMAView is a prefix");
+static_assert(offsetof(BandConst, ma_limb) + 5 * sizeof(float) == sizeof(BandMAView), "BandMAView is a prefix");
+static_assert(sizeof(BandMAView) == 64, "one 64-byte scalar load");
 
 // kPrecSurrogateBf16: the surrogate with bf16-only products (no hi/lo split)
 enum : int { kPrecFP64 = 0, kPrecFP32 = 1, kPrecSurrogate = 2, kPrecSurrogateBf16 = 3 };

@@ -373,7 +373,9 @@ hipError_t launch_gimenez(const double* z, int64_t n, double k, const double* u,
 PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
   BandConst c;
   c.kd = k;
+  c.c7d = 7.0 * k * k - 4.0;
   c.kf = float(k);
+  c.k2f = float(k * k);
   c.onepk = float(1.0 + k);
   c.omk = float(1.0 - k);
   c.inv1pkd = 1.0 / (1.0 + k);
@@ -404,7 +406,8 @@ PT_HD BandConst band_const(double k, const double* u, int nldc, int model) {
   if (!c.valid)
     for (int m = 0; m < 5; ++m) c.wd[m] = (double)NAN;
   for (int m = 0; m < 3; ++m) c.wf[m] = float(c.wd[m]);
-  c.pad = 0;
+  c.w1 = c.wf[1];
+  ma_loss_coefficients(k, c.wd[0], c.wd[1], c.wd[2], c.ma_in, c.ma_limb);
   return c;
 }
 
@@ -552,11 +555,18 @@ __device__ __noinline__ float ma_loss_outside_table(float z, float kf, double kd
   return w0 * r.le + w1 * r.ld + w2 * r.ed;
 }
 
-// The same from the leading part of the band's constants.
-__device__ __forceinline__ float ma_loss_view(float z, const BandMAView& v) {
+// The exact double path's loss at a point of the float path, out of line.
+__device__ __noinline__ float ma_loss_exact_band(float z, const BandConst* __restrict__ bc) {
+  const MaAlpha<double> r = ma_alpha_exact<double>(double(z), bc->kd);
+  return bc->wf[0] * float(r.le) + bc->wf[1] * float(r.ld) + bc->wf[2] * float(r.ed);
+}
+
+// The same from the leading part of the band's constants (v, read from bc),
+// the weights folded into per-band coefficients (ma_loss_mixed).
+__device__ __forceinline__ float ma_loss_view(float z, const BandMAView& v, const BandConst* __restrict__ bc) {
   if (z < 0.0f || z >= v.onepk) return 0.0f;
-  const MaAlpha<float> r = ma_alpha_fast(z, v.kf, v.kd, v.kd > 0.5, v.omk);
-  return v.w0 * r.le + v.w1 * r.ld + v.w2 * r.ed;
+  if (v.kd > 0.5 || fabsf(z - v.kf) < 1e-6f || fabsf(z - v.omk) < 1e-6f) return ma_loss_exact_band(z, bc);
+  return ma_loss_mixed(z, v.kd, v.c7d, v.kf, v.k2f, v.omk, v.onepk, v.w1, v.ma_in, v.ma_limb);
 }
 
 template <>
@@ -1081,8 +1091,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         if constexpr (F32 && MODEL == kModelMA) {
           for (int bnd = bb; bnd < be; ++bnd) {
             const BandMAView cur = load_uniform(reinterpret_cast<const BandMAView*>(a.bc + bnd));
-            const float acc = ma_loss_view(z1, cur);
-            const float f = cur.w0 == cur.w0 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
+            const float acc = ma_loss_view(z1, cur, a.bc + bnd);
+            const float f = cur.w1 == cur.w1 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
             if (act_lane) flux[fo + (int64_t)(bnd - b0) * cnt + i] = f;
           }
         } else {
@@ -1096,8 +1106,9 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
         }
       } else if (F32 && MODEL == kModelMA && !SUR && !LOGL && nss <= kZChunk) {
         // the float Mandel-Agol path: one orbit solve per (exposure,
-        // subsample), then per band only the leading 32 bytes of its
-        // constants (one scalar load instead of three: 0.564 -> 0.545 ms on
+        // subsample), then per band only the leading 64 bytes of its
+        // constants (one scalar load; in an earlier form, 32 bytes in one
+        // load instead of three took 0.564 -> 0.545 ms on
         // the spectrophotometric batch; loading the next band's before the
         // current band's model was slower, 0.585 ms, its wait shared with the
         // LDS reads of z)
@@ -1109,10 +1120,10 @@ __attribute__((amdgpu_waves_per_eu(PREC == kPrecFP64 && MODEL == kModelMA ? 4 : 
           for (int bnd = bb; bnd < be; ++bnd) {
             const BandMAView cur = load_uniform(reinterpret_cast<const BandMAView*>(a.bc + bnd));
             float acc = 0.0f;
-            if (ONE) acc = ma_loss_view(z1, cur);
+            if (ONE) acc = ma_loss_view(z1, cur, a.bc + bnd);
             else
-              for (int s = 0; s < nss; ++s) acc += ma_loss_view(zb[s * kWave + lane], cur);
-            const float f = cur.w0 == cur.w0 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
+              for (int s = 0; s < nss; ++s) acc += ma_loss_view(zb[s * kWave + lane], cur, a.bc + bnd);
+            const float f = cur.w1 == cur.w1 && orbit_ok ? 1.0f - acc * float(inv_nss) : NAN;
             if (act_lane) flux[fo + (int64_t)(bnd - b0) * cnt + i] = f;
           }
         };

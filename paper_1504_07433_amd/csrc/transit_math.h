@@ -719,8 +719,10 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 // reciprocal then takes the prefactor's square root with it.
 template <class T> struct MaEllTerms { T kc, ck, ce, sp, cp, bt2, pq; };
 
+// c7 = 7 k^2 - 4, the radius ratio's part of C_E (formed once per band by the
+// float path).
 template <class T, class Op>
-PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
+PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
   const T zmk = z - k, zpk = z + k;
   const T z2 = z * z, k2 = k * k;
   const T azmk = fabs(zmk);
@@ -733,7 +735,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
     const T bm1 = (zpk - T(1)) * (zpk + T(1));              // b - 1
     kc = bm1 > T(0) ? bm1 * Op::rsqrt(bm1 * (T(4) * z * k)) : T(0);   // sqrt((b-1)/(4zk))
     ck = (T(1) - b) * (T(2) * b + a - T(3)) - T(3) * q * (b - T(2));
-    ce = T(4) * z * k * (z2 + T(7) * k2 - T(4));
+    ce = T(4) * z * k * (z2 + c7);
     sp = rz;                                              // sqrt(p) = sqrt(1/a)
     pq = k * z;                                           // pref = 1 / (9 pi sqrt(k z))
     bt2 = T(3) * zpk * sgn;                               // C_P / sqrt(p)
@@ -743,7 +745,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
     const T omb = (T(1) - zpk) * (T(1) + zpk);              // 1 - b
     kc = omb > T(0) ? omb * Op::rsqrt(omb * oma) : T(0);    // sqrt((1-b)/(1-a))
     ck = T(1) - T(5) * z2 + k2 + q * q;
-    ce = oma * (z2 + T(7) * k2 - T(4));
+    ce = oma * (z2 + c7);
     sp = zpk * rz;                                        // sqrt(p) = sqrt(b/a)
     pq = T(0.25) * oma;                                   // pref = 2 / (9 pi sqrt(1 - a))
     bt2 = T(3) * sgn;                                     // C_P / sqrt(p)
@@ -753,17 +755,27 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
   return MaEllTerms<T>{kc, ck, ce, sp, cp, bt2, pq};
 }
 
+template <class T, class Op>
+PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb) {
+  return ma_elliptic_terms<T, Op>(z, k, limb, T(7) * k * k - T(4));
+}
+
 // In double, K and E come from the mean that drives the third-kind integral
 // (cel_agm_ke); otherwise C_K K + C_E E is one cel with p = 1 beside it.
 template <class T, int ITERS, class Op = Num<T>>
-PT_HD T ma_elliptic(T z, T k, bool limb) {
-  const MaEllTerms<T> e = ma_elliptic_terms<T, Op>(z, k, limb);
+PT_HD T ma_elliptic(T z, T k, bool limb, T c7) {
+  const MaEllTerms<T> e = ma_elliptic_terms<T, Op>(z, k, limb, c7);
   if constexpr (std::is_same<T, double>::value && ITERS == 0) {
     return cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.cp, e.bt2, e.pq);
   } else {
     const CelPair<T> r = cel2<T, ITERS, Op>(e.kc, T(1), e.ck + e.ce, e.ck + e.ce * e.kc * e.kc, e.sp, e.cp, e.bt2);
     return T(1.0 / (9.0 * kPi)) * Op::rsqrt(e.pq) * (r.r1 + r.r2);
   }
+}
+
+template <class T, int ITERS, class Op = Num<T>>
+PT_HD T ma_elliptic(T z, T k, bool limb) {
+  return ma_elliptic<T, ITERS, Op>(z, k, limb, T(7) * k * k - T(4));
 }
 
 // lambda_e and eta_1 in the limb region, with the square root of
@@ -791,7 +803,9 @@ PT_HD void ma_limb_terms(T z, T k, T* le, T* ed) {
 PT_HD MaAlpha<float> ma_alpha_mixed(float zf, float kf, double k) {
   MaAlpha<float> r;
   const double z = zf;
-  const bool limb = z > 1.0 - k;
+  // the side of z = 1 - k in float: the callers take the exact path within
+  // 1e-6 of it, far beyond the float rounding of 1 - k
+  const bool limb = zf > 1.0f - kf;
   const double ell = ma_elliptic<double, 0, NumFast>(z, k, limb);
   if (limb) {
     ma_limb_terms<float>(zf, kf, &r.le, &r.ed);
@@ -803,6 +817,49 @@ PT_HD MaAlpha<float> ma_alpha_mixed(float zf, float kf, double k) {
     r.ld = float(ell + (z < k ? 2.0 / 3.0 : 0.0));
   }
   return r;
+}
+
+// Per-band coefficients of the float path's Mandel-Agol loss, the flux
+// deficit w0 lambda_e + w1 lambda_d + w2 eta_d of a band with weights
+// w0, w1, w2 (Sect. 2.2.1), with the weights folded into the polynomials in
+// z that multiply the point's own parts.  Inside the disc lambda_e = k^2 and
+// eta_d = k^2 (k^2 + 2 z^2)/2, so the loss is in[0] + in[1] z^2 + w1 lambda_d.
+// On the limb, with lambda_e and eta_d from the angles kappa_0, kappa_1 and
+// sqrt(D) (ma_limb_terms), it is
+//   limb[0] kappa_1 + (limb[1] + limb[2] z^2) kappa_0
+//     + (limb[3] + limb[4] z^2) sqrt(D) + w1 lambda_d.
+PT_HD void ma_loss_coefficients(double k, double w0, double w1, double w2, float in[2], float limb[5]) {
+  const double k2 = k * k, ip = 1.0 / kPi;
+  in[0] = float(w0 * k2 + 0.5 * w2 * k2 * k2);
+  in[1] = float(w2 * k2);
+  limb[0] = float((w0 + 0.5 * w2) * ip);
+  limb[1] = float(k2 * (w0 + 0.5 * w2 * k2) * ip);
+  limb[2] = float(w2 * k2 * ip);
+  limb[3] = float(-(0.5 * w0 + 0.125 * w2 * (1.0 + 5.0 * k2)) * ip);
+  limb[4] = float(-0.125 * w2 * ip);
+}
+
+// The float path's loss at zf from those coefficients: lambda_d's elliptic
+// combination in double through NumFast (c7 = 7 k^2 - 4), with the 2/3 step
+// for z < k added before it is rounded to float, the rest in float
+// (k2 = k^2 in float).  Valid for k <= 1/2, 0 <= z < 1 + k, away from z = k
+// and z = 1 - k, where the callers take the exact path (so the two sides of
+// z = 1 - k and of z = k are told apart in float).
+PT_HD float ma_loss_mixed(float zf, double k, double c7, float kf, float k2, float omk, float onepk, float w1,
+                          const float in[2], const float limb[5]) {
+  const bool on_limb = zf > omk;
+  const double ell = ma_elliptic<double, 0, NumFast>(double(zf), k, on_limb, c7);
+  const float ld = float(zf < kf ? ell + 2.0 / 3.0 : ell);
+  const float z2 = zf * zf;
+  if (on_limb) {
+    float D = (zf - omk) * (onepk - zf) * (zf + omk) * (zf + onepk);
+    D = D > 0.0f ? D : 0.0f;
+    const float sD = Num<float>::sqrt(D);
+    const float kap0 = Num<float>::atan2(sD, k2 + z2 - 1.0f);
+    const float kap1 = Num<float>::atan2_narrow(sD, 1.0f - k2 + z2);
+    return limb[0] * kap1 + fmaf(limb[2], z2, limb[1]) * kap0 + fmaf(limb[4], z2, limb[3]) * sD + w1 * ld;
+  }
+  return fmaf(in[1], z2, in[0]) + w1 * ld;
 }
 
 // Complete elliptic integrals K(m), E(m) by cel (p = 1).

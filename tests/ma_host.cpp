@@ -19,4 +19,15 @@ void ma_alpha64(int n, const double* z, double k, int exact, double* out) {
   }
 }
 
+// The float path's loss w0 lambda_e + w1 lambda_d + w2 eta_d of one band from
+// its folded coefficients (ma_loss_coefficients, ma_loss_mixed), z rounded
+// to float.
+void ma_loss64(int n, const double* z, double k, double w0, double w1, double w2, double* out) {
+  float in[2], limb[5];
+  pt::ma_loss_coefficients(k, w0, w1, w2, in, limb);
+  const float kf = (float)k, k2 = (float)(k * k), omk = (float)(1.0 - k), onepk = (float)(1.0 + k);
+  for (int i = 0; i < n; ++i)
+    out[i] = pt::ma_loss_mixed((float)z[i], k, 7.0 * k * k - 4.0, kf, k2, omk, onepk, (float)w1, in, limb);
+}
+
 }

@@ -24,6 +24,8 @@ def lib(tmp_path_factory):
     dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
     L.ma_alpha64.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
     L.ma_alpha64.restype = None
+    L.ma_loss64.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    L.ma_loss64.restype = None
     return L
 
 
@@ -63,3 +65,27 @@ def test_mixed_bulk_form(lib, oracle, k):
     # seeds in lambda_d's elliptic combination; with flux weights <= 2.4 over
     # the physical quadratic laws 2e-7 keeps the flux within 4.8e-7
     assert d.max() <= 2e-7, (d.max(), z[np.argmax(d)])
+
+
+# (u1, u2): a typical law, a uniform source, the linear law's extreme, a
+# negative u2, and the largest weight of lambda_d over the physical laws
+@pytest.mark.parametrize("u1,u2", [(0.4, 0.2), (0.0, 0.0), (1.0, 0.0), (0.9, -0.3), (0.0, 1.0)])
+@pytest.mark.parametrize("k", [k for k in KS if k <= 0.5])
+def test_folded_loss(lib, oracle, k, u1, u2):
+    """The float path's loss with the weights folded into per-band
+    coefficients equals w0 lambda_e + w1 lambda_d + w2 eta_d of the oracle's
+    functions, weights (1 - c)/N, c/N, u2/N with c = u1 + 2 u2 and
+    N = 1 - u1/3 - u2/6, to the float path's own accuracy."""
+    kf = float(np.float32(k))
+    z = _grid(kf).astype(np.float32).astype(np.float64)
+    z = z[(z < 1.0 + kf) & (np.abs(z - kf) >= 1e-6) & (np.abs(z - (1.0 - kf)) >= 1e-6)]
+    n = 1.0 - u1 / 3.0 - u2 / 6.0
+    c = u1 + 2.0 * u2
+    w = np.array([(1.0 - c) / n, c / n, u2 / n])
+    got = np.empty(len(z))
+    lib.ma_loss64(len(z), np.ascontiguousarray(z), kf, w[0], w[1], w[2], got)
+    ref = oracle.ma_alpha_many(z, kf) @ w
+    d = np.abs(got - ref)
+    # within the float path's flux tolerance (1e-6) by a factor of two
+    assert d.max() <= 5e-7, (d.max(), z[np.argmax(d)])
+
