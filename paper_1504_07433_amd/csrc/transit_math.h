@@ -303,19 +303,20 @@ PT_HD CelPair<T> cel2(T kc, T sp1, T a1, T bt1, T sp2, T a2, T bt2) {
 // m = 1 - kc^2 and c_(j+1) = (a_j - g_j) / 2 = (mu_j - kk_j) / 2^(j+1); so only
 // the third-kind integral carries its own (p, a, b) through the steps, and
 // no step needs the product of two p.  The arguments are ckce = c_K + c_E,
-// ce8 = -c_E / 8, sqrt(p) and b / sqrt(p); the result is scaled by
+// ce8 = -c_E / 8, sqrt(p), its reciprocal rsp (the first step's, formed by
+// the caller without a division) and b / sqrt(p); the result is scaled by
 // 1 / (9 pi sqrt(pq)), taken with the final reciprocal as one reciprocal
 // square root.  On exit after steps 0..J, mu is 2^(J+1) times the next arithmetic
 // mean, whose relative distance from M is about (a_J - g_J)^2 / (16 a_J^2):
 // the same convergence test as cel.
 template <class Op>
-PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a, double bt, double pq) {
+PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double rsp, double a, double bt,
+                        double pq) {
   double mu = 1.0, kk = kc, prod = kc;
   double p = sp, b = bt;
   double s8 = 4.0 * fma(-kc, kc, 1.0);   // 8 sum 2^(n-1) c_n^2, so far n = 0
   double w = 2.0;                        // 8 / 2^(j+2): weight of (mu_j - kk_j)^2 in s8
-  auto step = [&](bool check) {
-    const double r = Op::rcp(p);
+  auto step = [&](double r, bool check) {   // r = 1 / p
     const double g = prod * r;
     const double f = a;
     a = fma(b, r, a);
@@ -331,10 +332,12 @@ PT_HD double cel_agm_ke(double kc, double ckce, double ce8, double sp, double a,
     prod = kk * mu;
     return true;
   };
-  int it = 0;
-  for (; it < Op::cel_unchecked; ++it) step(false);
-  for (; it < 40; ++it)
-    if (!step(true)) break;
+  if (step(rsp, Op::cel_unchecked == 0)) {
+    int it = 1;
+    for (; it < Op::cel_unchecked; ++it) step(Op::rcp(p), false);
+    for (; it < 40; ++it)
+      if (!step(Op::rcp(p), true)) break;
+  }
   // w = 2^-J now: K = pi 2^J / mu = pi / (mu w), and the third-kind integral
   // is (pi/2) (b + a mu) / (mu (mu + p)); one reciprocal for both and the
   // prefactor, pi / (9 pi sqrt(pq) X) = (1/9) / sqrt(pq X^2) with
@@ -717,7 +720,7 @@ template <class T> struct MaAlpha { T le, ld, ed; };
 // p = 1 - n; C_K K + C_E E is a second cel with p = 1, or, in double, comes
 // from the mean that the first one runs (ma_elliptic), whose last
 // reciprocal then takes the prefactor's square root with it.
-template <class T> struct MaEllTerms { T kc, ck, ce, sp, cp, bt2, pq; };
+template <class T> struct MaEllTerms { T kc, ck, ce, sp, rsp, cp, bt2, pq; };
 
 // c7 = 7 k^2 - 4, the radius ratio's part of C_E (formed once per band by the
 // float path).
@@ -727,9 +730,14 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
   const T z2 = z * z, k2 = k * k;
   const T azmk = fabs(zmk);
   const T sgn = zmk > T(0) ? T(1) : T(-1);
-  const T rz = Op::rcp(azmk);                              // 1 / |z-k| = sqrt(1/a)
+  // rz = 1 / |z-k| = sqrt(1/a), and rsp = 1 / sqrt(p) for the mean's first
+  // step: on the limb |z-k| itself; inside |z-k| / (z+k), both sharing one
+  // reciprocal of |z-k| (z+k)
+  T rz, rsp;
   T kc, ck, ce, sp, pq, bt2;
   if (limb) {
+    rz = Op::rcp(azmk);
+    rsp = azmk;
     const T a = zmk * zmk, b = zpk * zpk;
     const T q = (k - z) * (k + z);
     const T bm1 = (zpk - T(1)) * (zpk + T(1));              // b - 1
@@ -740,6 +748,9 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
     pq = k * z;                                           // pref = 1 / (9 pi sqrt(k z))
     bt2 = T(3) * zpk * sgn;                               // C_P / sqrt(p)
   } else {
+    const T rr = Op::rcp(azmk * zpk);
+    rz = zpk * rr;
+    rsp = azmk * azmk * rr;
     const T q = (k - z) * (k + z);
     const T oma = (T(1) - zmk) * (T(1) + zmk);              // 1 - a
     const T omb = (T(1) - zpk) * (T(1) + zpk);              // 1 - b
@@ -752,7 +763,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
   }
   // C_P = -3 q / a = 3 (z+k) / (z-k) = 3 sign(z-k) (z+k) / |z-k|
   const T cp = T(3) * sgn * zpk * rz;
-  return MaEllTerms<T>{kc, ck, ce, sp, cp, bt2, pq};
+  return MaEllTerms<T>{kc, ck, ce, sp, rsp, cp, bt2, pq};
 }
 
 template <class T, class Op>
@@ -766,7 +777,7 @@ template <class T, int ITERS, class Op = Num<T>>
 PT_HD T ma_elliptic(T z, T k, bool limb, T c7) {
   const MaEllTerms<T> e = ma_elliptic_terms<T, Op>(z, k, limb, c7);
   if constexpr (std::is_same<T, double>::value && ITERS == 0) {
-    return cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.cp, e.bt2, e.pq);
+    return cel_agm_ke<Op>(e.kc, e.ck + e.ce, -0.125 * e.ce, e.sp, e.rsp, e.cp, e.bt2, e.pq);
   } else {
     const CelPair<T> r = cel2<T, ITERS, Op>(e.kc, T(1), e.ck + e.ce, e.ck + e.ce * e.kc * e.kc, e.sp, e.cp, e.bt2);
     return T(1.0 / (9.0 * kPi)) * Op::rsqrt(e.pq) * (r.r1 + r.r2);
