@@ -44,8 +44,11 @@ SURROGATE_CKPT = os.path.join(ROOT, "paper_1504_07433_amd", "data", "surrogate.n
 # profiles/unit_probes_flops.txt):
 F_ORBIT_ECC = 86.0        # orbit of one in-transit point, e > 0: Kepler, z (float part)
 F_ORBIT_CIRC = 40.0       # the same for e = 0
-F_MA_INSIDE = 191.5       # Mandel-Agol functions + limb darkening, z < 1 - k
-F_MA_LIMB = 283.3         # the same, 1 - k < z < 1 + k
+# The Mandel-Agol work per (point, band) is the batch kernel's own: the
+# difference between the two-band and one-band probes (batch-in-2band and
+# batch-in, batch-limb-2band and batch-limb).
+F_MA_INSIDE = 136.0       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 199.0         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8);
 # each further band of a point out of transit its accumulation and flux (2).
@@ -58,9 +61,9 @@ F_POINT, F_EXPOSURE, F_BAND_OUT = 5.0, 8.0, 2.0
 # in-transit point (phase, one Kepler solve, series coefficients, flux).  The
 # probes run at series order 4; order-5 light curves spend ~4 flops more per
 # point and ~20 more per exposure, which the model does not charge.
-F_SER_INSIDE = 152.9
-F_SER_LIMB = 238.9
-F_SER_EXPOSURE = 228.3
+F_SER_INSIDE = 147.0
+F_SER_LIMB = 209.0
+F_SER_EXPOSURE = 218.0
 SERIES_NSS = (4, 16)
 # MI355X published peaks.  The FP32 vector peak counts packed FP32 FMAs (two
 # per lane per cycle); this build compiles with packed FP32 disabled, so the
@@ -84,9 +87,9 @@ NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 # counters read for an elementwise kernel that reads and writes 1 GiB
 # (FETCH_SIZE 524309.7 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB written).
 COUNTERS = {
-    "spectrophotometric": {"valu_insts": 1.76871e8, "fetch_kib": 71773.6, "write_kib": 464609.0},
-    "long-cadence": {"valu_insts": 8.06182e8, "fetch_kib": 10626.4, "write_kib": 204399.0},
-    "uneven": {"valu_insts": 6.86191e9, "fetch_kib": 381192.0, "write_kib": 2845500.0},
+    "spectrophotometric": {"valu_insts": 1.59150e8, "fetch_kib": 96033.3, "write_kib": 455928.0},
+    "long-cadence": {"valu_insts": 7.47405e8, "fetch_kib": 10906.4, "write_kib": 204400.0},
+    "uneven": {"valu_insts": 6.25958e9, "fetch_kib": 410190.0, "write_kib": 2859100.0},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524309.7, 1.0
 
@@ -126,6 +129,11 @@ def unit_probes():
       gim-inside  float Gimenez, npol = 50, two coefficients, z in (0, 1-k)
       batch-cut   batch kernel, one light curve whose window holds no point
       batch-in    batch kernel, e = 0.2, every point inside the disc
+      batch-limb  the same with b = 1, every point on the limb
+      batch-in-2band, batch-limb-2band
+                  the same with two bands (2^23 points, each in both bands):
+                  the difference to the one-band launch is the Mandel-Agol
+                  work per (point, band) of the batch kernel
       batch-series-4, batch-series-16
                   the same with 4 / 16 subsamples per exposure (0.01 d), the
                   orbit from the per-exposure position series
@@ -137,8 +145,8 @@ def unit_probes():
     from paper_1504_07433_amd import pthip, workloads as W
     n = 1 << 24
 
-    def one_lc(b_imp, e, span, nss=1, t_exp=0.0):
-        ne = n // nss
+    def one_lc(b_imp, e, span, nss=1, t_exp=0.0, bands=1):
+        ne = n // nss // bands
         b = W.config1()
         b["t"] = np.linspace(-span, span, ne)
         b["t_count"] = np.array([ne], np.int64)
@@ -146,7 +154,8 @@ def unit_probes():
         b["t_exp"] = np.array([t_exp])
         b["b"] = np.array([b_imp]); b["e"] = np.array([e]); b["w"] = np.array([1.0])
         b["aR"] = np.array([10.0]); b["P"] = np.array([3.0]); b["t0"] = np.array([0.0])
-        b["k"] = np.array([0.1]); b["u"] = np.array([[0.4, 0.2]]); b["n_flux"] = ne
+        b["k"] = np.full(bands, 0.1); b["u"] = np.tile([[0.4, 0.2]], (bands, 1)); b["n_flux"] = ne * bands
+        b["band_off"] = np.array([0, bands], np.int32)
         return b
 
     def report(name, out):
@@ -171,6 +180,8 @@ def unit_probes():
     report("gim-inside", f)
     del zz, f, t, z
     for name, b in (("batch-cut", one_lc(1.5, 0.0, 0.04)), ("batch-in", one_lc(0.3, 0.2, 0.03)),
+                    ("batch-in-2band", one_lc(0.3, 0.2, 0.03, bands=2)),
+                    ("batch-limb", one_lc(1.0, 0.2, 0.01)), ("batch-limb-2band", one_lc(1.0, 0.2, 0.01, bands=2)),
                     ("batch-series-4", one_lc(0.3, 0.2, 0.025, 4, 0.01)),
                     ("batch-series-16", one_lc(0.3, 0.2, 0.025, 16, 0.01)),
                     ("batch-series-limb-16", one_lc(1.0, 0.2, 0.01, 16, 0.01))):
