@@ -397,10 +397,17 @@ PT_HD OrbitConst orbit_const(double t0, double P, double aR, double b, double e,
   o.sq1me2 = ::sqrt(1.0 - e * e);
   o.cw = ::cos(w);
   o.sw = ::sin(w);
-  const double fc = 0.5 * kPi - w;
-  const double Ec = 2.0 * ::atan2(::sqrt(1.0 - e) * ::sin(0.5 * fc), ::sqrt(1.0 + e) * ::cos(0.5 * fc));
-  o.cEc = ::cos(Ec);
-  o.sEc = ::sin(Ec);
+  if (e == 0.0) {
+    // circular: the eccentric anomaly at conjunction is the true one,
+    // pi/2 - w, so its cosine and sine are sin w and cos w
+    o.cEc = o.sw;
+    o.sEc = o.cw;
+  } else {
+    const double fc = 0.5 * kPi - w;
+    const double Ec = 2.0 * ::atan2(::sqrt(1.0 - e) * ::sin(0.5 * fc), ::sqrt(1.0 + e) * ::cos(0.5 * fc));
+    o.cEc = ::cos(Ec);
+    o.sEc = ::sin(Ec);
+  }
   o.rc = 1.0 - e * o.cEc;
   o.d1 = 1.0 - e * o.cEc;  // dM/dx at conjunction
   o.inv_d1 = 1.0 / o.d1;
@@ -418,7 +425,7 @@ PT_HD OrbitConst orbit_const(double t0, double P, double aR, double b, double e,
   if (k_max >= 0.0) {
     const double s = (1.0 + k_max) / (aR * (1.0 - e));
     if (s < 1.0) {
-      const double c = ::pow(1.0 + e, 1.5) / ::sqrt(1.0 - e) * ::asin(s);
+      const double c = (e == 0.0 ? 1.0 : ::pow(1.0 + e, 1.5) / ::sqrt(1.0 - e)) * ::asin(s);
       o.dm_cut = c * (1.0 + 1e-6) + 1e-9;
     }
   }
