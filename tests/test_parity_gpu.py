@@ -391,6 +391,28 @@ def test_batch_eccentric_contacts(pt, O, nss, t_exp):
     assert np.abs(got - ref).max() <= TOL32
 
 
+# quadratic laws at the edges of the physical region (u1 >= 0, u1 + u2 <= 1,
+# u1 + 2 u2 >= 0) and a typical one: the weight of lambda_d runs from 0
+# (u = (2, -1)) to 2.4 (u = (0, 1)), the largest it takes
+EXTREME_LAWS = [(0.4, 0.2), (0.0, 0.0), (1.0, 0.0), (0.0, 1.0), (2.0, -1.0), (0.9, -0.3)]
+
+
+@pytest.mark.parametrize("nss,t_exp", [(1, 0.0), (7, 0.0204)])
+def test_batch_extreme_laws_dense_contacts(pt, O, nss, t_exp):
+    """The float path's loss with the weights folded into per-band
+    coefficients, for laws at the edges of the physical region, on orbits
+    with times dense around every contact (one subsample: the one-subsample
+    kernel; seven: the general kernel)."""
+    b = _contact_batch(O, 41 + nss, 0.6, nss, t_exp)
+    nb = len(b["k"])
+    b["u"] = np.array([EXTREME_LAWS[j % len(EXTREME_LAWS)] for j in range(nb)], np.float64)
+    ref = O.lc_batch(b, model=0)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        got = _run(pt, b, "ma", prec)
+        say("extreme laws", prec, "nss", nss, "max|dF|", np.abs(got - ref).max())
+        assert np.abs(got - ref).max() <= tol, prec
+
+
 def test_batch_nonphysical_parameters_give_nan(pt):
     from paper_1504_07433_amd import workloads as W
     b = W.config2(n_vec=4, n_windows=1)
