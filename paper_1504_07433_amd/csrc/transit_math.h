@@ -64,14 +64,10 @@ template <> struct Num<float> {
     return 1.0f / ::sqrtf(x);
 #endif
   }
-  // atan2 for y >= 0 (upper half plane): t = min(|x|, y) / max(|x|, y) in
-  // [0, 1], atan t by an odd polynomial of degree 17 whose coefficients were
-  // fitted to atan on [0, 1] by Lawson's iteratively reweighted least squares
-  // (maximum error 5.8e-9), then the octant is restored.
-  PT_HD static float atan2(float y, float x) {
-    const float ax = fabsf(x);
-    const float lo = fminf(ax, y), hi = fmaxf(ax, y);
-    const float t = hi > 0.0f ? lo * rcp(hi) : 0.0f;
+  // atan t for t in [0, 1]: an odd polynomial of degree 17 whose
+  // coefficients were fitted to atan on [0, 1] by Lawson's iteratively
+  // reweighted least squares (maximum error 5.8e-9).
+  PT_HD static float atan_unit(float t) {
     const float t2 = t * t;
     float p = 2.456725429e-03f;
     p = p * t2 - 1.440136161e-02f;
@@ -82,16 +78,12 @@ template <> struct Num<float> {
     p = p * t2 + 1.998590678e-01f;
     p = p * t2 - 3.333259703e-01f;
     p = p * t2 + 9.999998864e-01f;
-    float r = t * p;
-    r = y > ax ? 1.57079632679489662f - r : r;
-    return x < 0.0f ? 3.14159265358979324f - r : r;
+    return t * p;
   }
-  // atan2 for 0 <= y <= x / sqrt(3) (an angle of at most 30 degrees): atan of
-  // t = y / x by an odd polynomial of degree 11 fitted to atan on
-  // [0, 0.578] by Lawson's iteratively reweighted least squares (maximum
-  // error 5.7e-9).
-  PT_HD static float atan2_narrow(float y, float x) {
-    const float t = y * rcp(x);
+  // atan t for t in [0, 1/sqrt(3)] (an angle of at most 30 degrees): an odd
+  // polynomial of degree 11 fitted to atan on [0, 0.578] the same way
+  // (maximum error 5.7e-9).
+  PT_HD static float atan_narrow(float t) {
     const float t2 = t * t;
     float p = -4.0179652225e-02f;
     p = p * t2 + 9.3659724248e-02f;
@@ -100,6 +92,30 @@ template <> struct Num<float> {
     p = p * t2 - 3.3332188301e-01f;
     p = p * t2 + 9.9999986908e-01f;
     return t * p;
+  }
+  // the octant of atan2(y, x), y >= 0, from r = atan(min(|x|, y) / max(|x|, y))
+  PT_HD static float atan2_octant(float r, float y, float x) {
+    r = y > fabsf(x) ? 1.57079632679489662f - r : r;
+    return x < 0.0f ? 3.14159265358979324f - r : r;
+  }
+  // atan2 for y >= 0 (upper half plane)
+  PT_HD static float atan2(float y, float x) {
+    const float ax = fabsf(x);
+    const float lo = fminf(ax, y), hi = fmaxf(ax, y);
+    const float t = hi > 0.0f ? lo * rcp(hi) : 0.0f;
+    return atan2_octant(atan_unit(t), y, x);
+  }
+  // atan2 for 0 <= y <= x / sqrt(3)
+  PT_HD static float atan2_narrow(float y, float x) { return atan_narrow(y * rcp(x)); }
+  // atan2(y, x0) for y >= 0 and atan2_narrow(y, x1), the two quotients from
+  // one reciprocal, of max(|x0|, y) x1
+  PT_HD static void atan2_and_narrow(float y, float x0, float x1, float* a0, float* a1) {
+    const float ax = fabsf(x0);
+    const float lo = fminf(ax, y), hi = fmaxf(ax, y);
+    const float r = rcp(hi * x1);
+    const bool some = hi > 0.0f;              // else y = 0 = x0: both angles 0
+    *a0 = atan2_octant(atan_unit(some ? lo * (x1 * r) : 0.0f), y, x0);
+    *a1 = atan_narrow(some ? y * (hi * r) : 0.0f);
   }
   PT_HD static void sincos(float x, float* s, float* c) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -736,7 +752,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
   const T zmk = z - k, zpk = z + k;
   const T z2 = z * z, k2 = k * k;
   const T azmk = fabs(zmk);
-  const T sgn = zmk > T(0) ? T(1) : T(-1);
+  const T s3 = copysign(T(3), zmk);                        // 3 sign(z-k); z != k here
   // rz = 1 / |z-k| = sqrt(1/a), and rsp = 1 / sqrt(p) for the mean's first
   // step: on the limb |z-k| itself; inside |z-k| / (z+k), both sharing one
   // reciprocal of |z-k| (z+k)
@@ -753,7 +769,7 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
     ce = T(4) * z * k * (z2 + c7);
     sp = rz;                                              // sqrt(p) = sqrt(1/a)
     pq = k * z;                                           // pref = 1 / (9 pi sqrt(k z))
-    bt2 = T(3) * zpk * sgn;                               // C_P / sqrt(p)
+    bt2 = s3 * zpk;                                       // C_P / sqrt(p)
   } else {
     const T rr = Op::rcp(azmk * zpk);
     rz = zpk * rr;
@@ -766,10 +782,10 @@ PT_HD MaEllTerms<T> ma_elliptic_terms(T z, T k, bool limb, T c7) {
     ce = oma * (z2 + c7);
     sp = zpk * rz;                                        // sqrt(p) = sqrt(b/a)
     pq = T(0.25) * oma;                                   // pref = 2 / (9 pi sqrt(1 - a))
-    bt2 = T(3) * sgn;                                     // C_P / sqrt(p)
+    bt2 = s3;                                             // C_P / sqrt(p)
   }
   // C_P = -3 q / a = 3 (z+k) / (z-k) = 3 sign(z-k) (z+k) / |z-k|
-  const T cp = T(3) * sgn * zpk * rz;
+  const T cp = s3 * zpk * rz;
   return MaEllTerms<T>{kc, ck, ce, sp, rsp, cp, bt2, pq};
 }
 
@@ -873,8 +889,8 @@ PT_HD float ma_loss_mixed(float zf, double k, double c7, float kf, float k2, flo
     float D = (zf - omk) * (onepk - zf) * (zf + omk) * (zf + onepk);
     D = D > 0.0f ? D : 0.0f;
     const float sD = Num<float>::sqrt(D);
-    const float kap0 = Num<float>::atan2(sD, k2 + z2 - 1.0f);
-    const float kap1 = Num<float>::atan2_narrow(sD, 1.0f - k2 + z2);
+    float kap0, kap1;
+    Num<float>::atan2_and_narrow(sD, k2 + z2 - 1.0f, 1.0f - k2 + z2, &kap0, &kap1);
     return limb[0] * kap1 + fmaf(limb[2], z2, limb[1]) * kap0 + fmaf(limb[4], z2, limb[3]) * sD + w1 * ld;
   }
   return fmaf(in[1], z2, in[0]) + w1 * ld;
