@@ -47,8 +47,8 @@ F_ORBIT_CIRC = 40.0       # the same for e = 0
 # The Mandel-Agol work per (point, band) is the batch kernel's own: the
 # difference between the two-band and one-band probes (batch-in-2band and
 # batch-in, batch-limb-2band and batch-limb).
-F_MA_INSIDE = 136.0       # Mandel-Agol functions + limb darkening, z < 1 - k
-F_MA_LIMB = 199.0         # the same, 1 - k < z < 1 + k
+F_MA_INSIDE = 135.0       # Mandel-Agol functions + limb darkening, z < 1 - k
+F_MA_LIMB = 198.0         # the same, 1 - k < z < 1 + k
 # Every point also pays the subsample offset of the mean anomaly and the
 # accumulation (5 flops) and, per exposure, the FP64 phase and the flux (8);
 # each further band of a point out of transit its accumulation and flux (2).
@@ -61,8 +61,8 @@ F_POINT, F_EXPOSURE, F_BAND_OUT = 5.0, 8.0, 2.0
 # in-transit point (phase, one Kepler solve, series coefficients, flux).  The
 # probes run at series order 4; order-5 light curves spend ~4 flops more per
 # point and ~20 more per exposure, which the model does not charge.
-F_SER_INSIDE = 147.0
-F_SER_LIMB = 209.0
+F_SER_INSIDE = 146.0
+F_SER_LIMB = 208.0
 F_SER_EXPOSURE = 218.0
 SERIES_NSS = (4, 16)
 # MI355X published peaks.  The FP32 vector peak counts packed FP32 FMAs (two
@@ -87,9 +87,9 @@ NET_PRODUCTS = 1 if os.environ.get("PT_MLP_SPLIT") == "0" else 3
 # counters read for an elementwise kernel that reads and writes 1 GiB
 # (FETCH_SIZE 524309.7 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB written).
 COUNTERS = {
-    "spectrophotometric": {"valu_insts": 1.59150e8, "fetch_kib": 96033.3, "write_kib": 455928.0},
-    "long-cadence": {"valu_insts": 7.47405e8, "fetch_kib": 10906.4, "write_kib": 204400.0},
-    "uneven": {"valu_insts": 6.25958e9, "fetch_kib": 410190.0, "write_kib": 2859100.0},
+    "spectrophotometric": {"valu_insts": 1.56781e8, "fetch_kib": 95989.4, "write_kib": 456081.0},
+    "long-cadence": {"valu_insts": 7.40083e8, "fetch_kib": 10963.7, "write_kib": 204913.0},
+    "uneven": {"valu_insts": 6.17812e9, "fetch_kib": 410279.0, "write_kib": 2860780.0},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524309.7, 1.0
 
