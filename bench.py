@@ -225,7 +225,7 @@ def count_units(pt, batch):
     per-exposure series (4..16 subsamples), plus their exposures holding an
     in-transit point."""
     import torch
-    c = dict.fromkeys(("orbit_points", "orbit_points_in_transit_ecc", "orbit_points_in_transit_circ",
+    c = dict.fromkeys(("orbit_points", "orbit_points_ecc", "orbit_points_in_transit_ecc", "orbit_points_in_transit_circ",
                        "inside_points", "limb_points", "band_points_out", "series_points_in_transit",
                        "series_exposures_in_transit", "series_inside_points", "series_limb_points"), 0)
     for i in range(len(batch["t_start"])):
@@ -245,6 +245,8 @@ def count_units(pt, batch):
         ins = int((front[None, :] & (z[None, :] <= 1 - ks[:, None])).sum().item())
         lim = int((front[None, :] & (z[None, :] > 1 - ks[:, None]) & (z[None, :] < 1 + ks[:, None])).sum().item())
         c["orbit_points"] += ts.numel()
+        if batch["e"][i] > 0:
+            c["orbit_points_ecc"] += ts.numel()
         c["orbit_points_in_transit_ecc" if batch["e"][i] > 0 else "orbit_points_in_transit_circ"] += n_tr
         c["inside_points"] += ins
         c["limb_points"] += lim
@@ -273,6 +275,18 @@ def unit_flops(u, n_exposures):
             + u["series_exposures_in_transit"] * F_SER_EXPOSURE)
 
 
+# The survey's per-unit estimates of the same work (before counting): an
+# orbit point 80 flops + 8 transcendentals with e > 0, 20 + 2 with e = 0; a
+# Mandel-Agol (point, band) in transit 250 + 20; one out of transit 5.
+S_ORBIT_ECC, S_ORBIT_CIRC, S_MA, S_OUT = 88.0, 22.0, 270.0, 5.0
+
+
+def survey_flops(u):
+    """Flops of one launch from the same units at the survey's estimates."""
+    return (u["orbit_points_ecc"] * S_ORBIT_ECC + (u["orbit_points"] - u["orbit_points_ecc"]) * S_ORBIT_CIRC
+            + (u["inside_points"] + u["limb_points"]) * S_MA + u["band_points_out"] * S_OUT)
+
+
 def alu_roofline(pt, batch, workload, kernel_s):
     """Roofline object of k_lc_batch<fp32, MA> on a workload: algorithmic
     flops per launch / the launch's event-timed duration against the
@@ -288,6 +302,10 @@ def alu_roofline(pt, batch, workload, kernel_s):
             "kernel": "k_lc_batch<fp32, MA> (+ the window kernel)", "kernel_ms": kernel_s * 1e3,
             "algorithmic_flops_per_launch": flops, **u,
             "hbm_bytes_algorithmic": hbm, "hbm_frac": hbm / kernel_s / HBM_PEAK}
+    # the same launch priced at the survey's per-unit estimates, for comparison
+    sf = survey_flops(u)
+    roof["survey_units"] = {"flops_per_launch": sf, "achieved": sf / kernel_s / 1e12,
+                            "frac": sf / kernel_s / PEAK_FP32, "frac_nonpacked": sf / kernel_s / PEAK_NONPACKED}
     cnt = COUNTERS.get(workload)
     if cnt:
         roof["traffic"] = (cnt["fetch_kib"] * FETCH_SCALE + cnt["write_kib"] * WRITE_SCALE) * 1024.0
