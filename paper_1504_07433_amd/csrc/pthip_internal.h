@@ -10,7 +10,7 @@
 namespace pt {
 
 // Per-passband constants of a batch, formed on the device each call.  The
-// first 32 bytes are what the float Mandel-Agol path reads per band
+// first 64 bytes are what the float Mandel-Agol path reads per band
 // (BandMAView, one scalar load); a band is valid when its radius ratio is
 // positive and its weights finite, and an invalid band has NaN weights.
 struct BandConst {
